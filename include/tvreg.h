@@ -1,0 +1,204 @@
+/*
+ * tvreg.h -- C ABI of the MI355X (gfx950) library for TV-regularised CT
+ * reconstruction: the per-iteration evaluation of
+ *
+ *     phi(x) = 1/2 |A x - b|_2^2 + alpha T_tau(x),   x in Q = {x >= 0},
+ *
+ * (Sec. II-A, eq. 1, with the TV of eq. 2 Huber-smoothed by tau) and its
+ * gradient, driven by the gradient projection method (Sec. III-A, eq. 6),
+ * GPBB (Alg. 1) and UPN (Alg. 3, with BT of Alg. 2 and the mu estimate of
+ * eq. 9), all stopped on the gradient map (Sec. III-D, eq. 10).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Volume x: nz x ny x nx, x fastest (index i + nx (j + ny k)); voxel
+ *    (i, j, k) is the unit box [i - nx/2, i + 1 - nx/2] x [j - ny/2, ...] x
+ *    [k - nz/2, ...], cells half-open.
+ *  - Projection data: n_views x det_rows x det_cols, column fastest.
+ *  - A (the paper's system matrix, left unspecified there): one ray through
+ *    each detector pixel centre, a_ij = exact length of ray i in voxel j.
+ *    View theta: e_s = (cos, sin, 0), e_u = (-sin, cos, 0), e_v = z; pixel
+ *    centre u = (col - (cols-1)/2) pitch_u, w = (row - (rows-1)/2) pitch_v.
+ *    Parallel beam: the line through u e_u + w e_v with direction e_s.
+ *    Cone beam: the segment from R e_s to -(SDD - R) e_s + u e_u + w e_v.
+ *  - Precision: TVREG_F32_RED64 stores vectors as float (32-bit) and forms
+ *    every inner product, objective value, step length, line-search test and
+ *    stop test in double; ray geometry is double in both modes.  TVREG_F64
+ *    is double throughout.  "T" below is float or double accordingly.
+ *  - Pointers named *_dev are device pointers (HIP); all device buffers are
+ *    owned by the caller.  Every call is asynchronous on `stream` (a
+ *    hipStream_t, NULL = default stream) unless stated otherwise.
+ *  - Errors: a negative status means nothing was written; tvreg_last_error()
+ *    returns a thread-local message.  A positive status means the outputs are
+ *    valid but flagged.
+ */
+#ifndef TVREG_H
+#define TVREG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TVREG_OK = 0,
+    TVREG_EINVAL = -1,   /* bad argument (dimension, pointer, parameter) */
+    TVREG_ENOMEM = -2,   /* workspace too small or allocation failed */
+    TVREG_EDEVICE = -3,  /* HIP runtime error */
+    TVREG_ENOTCONV = 1,  /* max_iter reached before the stop test held */
+    TVREG_ESTALL = 2     /* a line-search cap was hit; last accepted x returned */
+} tvreg_status;
+
+typedef enum { TVREG_PARALLEL = 0, TVREG_CONE = 1 } tvreg_beam;
+typedef enum { TVREG_F32_RED64 = 0, TVREG_F64 = 1 } tvreg_precision;
+typedef enum { TVREG_GP = 0, TVREG_GPBB = 1, TVREG_UPN = 2 } tvreg_method;
+
+/* Scan geometry (all lengths in voxel units, volume centred at the origin). */
+typedef struct {
+    int32_t nx, ny, nz;          /* volume size, each >= 1 */
+    int32_t n_views;             /* >= 1 */
+    const double *angles_rad;    /* host array of n_views view angles (copied) */
+    tvreg_beam beam;
+    int32_t det_cols, det_rows;  /* >= 1 */
+    double pitch_u, pitch_v;     /* > 0 */
+    double src_to_centre;        /* cone: R, must exceed the volume's half diagonal */
+    double src_to_det;           /* cone: SDD, SDD - R must exceed the half diagonal */
+} tvreg_geometry_desc;
+
+typedef struct tvreg_geometry tvreg_geometry; /* opaque, library-owned */
+
+/*
+ * Builds the device-side ray tables of a geometry (a few doubles per view,
+ * detector column and row; the only memory the library allocates).
+ * Returns TVREG_EINVAL for non-positive sizes or pitches, NULL pointers, or a
+ * cone whose source or detector is inside the volume's bounding sphere.
+ * Synchronous.
+ */
+tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *desc, tvreg_precision precision,
+                                   tvreg_geometry **out);
+void tvreg_destroy_geometry(tvreg_geometry *geom);
+
+/*
+ * y = A x  (the forward mapping of Sec. IV-A).  x_dev: N values of T,
+ * y_dev: m values of T (overwritten).  Ray sums accumulate in double.
+ */
+tvreg_status tvreg_project(const tvreg_geometry *geom, const void *x_dev, void *y_dev,
+                           void *stream);
+
+/*
+ * x = A^T r  (the data part of grad phi, Sec. III-A eq. 6 needs grad f).
+ * r_dev: m values of T; x_dev: N values of T (overwritten).  Computed as a
+ * gather: every voxel sums, view by view, the rays crossing it with the same
+ * lengths the projector uses, in a fixed order (run-to-run bitwise
+ * reproducible, no atomics).
+ */
+tvreg_status tvreg_backproject(const tvreg_geometry *geom, const void *r_dev, void *x_dev,
+                               void *stream);
+
+/* Bytes of device workspace tvreg_tv_grad and tvreg_objective_grad need. */
+size_t tvreg_tv_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
+
+/*
+ * grad_dev = grad T_tau(x) and, when tv_value_dev != NULL, *tv_value_dev =
+ * T_tau(x) as one double in device memory (eq. 2 smoothed:
+ * T_tau(x) = sum_j Phi_tau(D_j x), Phi_tau(z) = |z| - tau/2 for |z| >= tau,
+ * |z|^2/(2 tau) otherwise; D_j forward differences, zero across the upper
+ * volume faces).  workspace_dev may be NULL when tv_value_dev is NULL.
+ */
+tvreg_status tvreg_tv_grad(int32_t nx, int32_t ny, int32_t nz, tvreg_precision precision,
+                           double tau, const void *x_dev, void *grad_dev, double *tv_value_dev,
+                           void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* Bytes of device workspace tvreg_objective_grad needs for this geometry. */
+size_t tvreg_objective_workspace_bytes(const tvreg_geometry *geom);
+
+/*
+ * One gradient evaluation: grad_dev = A^T (A x - b) + alpha grad T_tau(x)
+ * and *phi_dev = 1/2 |A x - b|^2 + alpha T_tau(x) (double, device).
+ * b_dev: m values of T.
+ */
+tvreg_status tvreg_objective_grad(const tvreg_geometry *geom, const void *b_dev, double alpha,
+                                  double tau, const void *x_dev, void *grad_dev,
+                                  double *phi_dev, void *workspace_dev, size_t workspace_bytes,
+                                  void *stream);
+
+typedef struct {
+    tvreg_method method;
+    double alpha, tau;
+    double eps;              /* stop tolerance */
+    int32_t stop_mode;       /* 0: |G|/|G_0| <= eps;  1: |G|/N <= eps (as printed) */
+    int32_t max_iter;        /* outer iterations (BT or GPBB steps) */
+    double L_bar;            /* initial Lipschitz estimate (Alg. 2/3 input), > 0 */
+    double mu_bar;           /* UPN initial mu; <= 0 selects L_0 / 4 */
+    double rho_L;            /* BT growth factor, > 1 */
+    int32_t gpbb_K;          /* GPBB nonmonotone memory, 0..16 */
+    double gpbb_sigma;       /* GPBB sufficient-decrease weight */
+    double gpbb_beta0;       /* GPBB initial step fraction in (0, 1) */
+    int32_t max_trials;      /* cap on BT growths / GPBB squarings per iteration */
+    double *hist_phi;        /* optional host arrays of hist_len entries: phi of */
+    double *hist_gm;         /* each accepted point, |G|/|G_0| of each iteration, */
+    double *hist_L;          /* and the step's L (1/theta for GPBB) */
+    int32_t hist_len;
+} tvreg_solve_params;
+
+typedef struct {
+    int32_t iters;           /* outer iterations performed */
+    int32_t grad_evals;      /* evaluations of grad f (A^T and TV gradient) */
+    int32_t func_evals;      /* evaluations of f at trial points (A and TV value) */
+    double phi;              /* phi at the returned x */
+    double gm_rel;           /* last |G| / |G_0| */
+    double gm_abs_over_N;    /* last |G| / N (the printed stop quantity) */
+    double L, mu;            /* final Lipschitz and strong-convexity estimates */
+    int32_t stop_reason;     /* tvreg_status of the run */
+} tvreg_solve_info;
+
+/* Bytes of device workspace tvreg_solve needs for this geometry and method. */
+size_t tvreg_solve_workspace_bytes(const tvreg_geometry *geom, tvreg_method method);
+
+/*
+ * Solves min_{x >= 0} phi(x) with GP (eq. 6, step 1/L_k from BT warm-started
+ * at L_{k-1}), GPBB (Alg. 1) or UPN (Alg. 3).  x_inout_dev holds x_0 on entry
+ * (negative entries are clipped) and the last accepted iterate on return.
+ * b_dev: m values of T.  The line-search decisions and the mu estimate are
+ * evaluated in the rearranged form Bregman_f(x, y) vs L/2 |x - y|^2 (the
+ * same inequality as Alg. 2 / eq. 9 without subtracting two objective
+ * values).  Synchronises `stream` once per line-search trial and before
+ * returning; `info` is written on the host.  Returns TVREG_OK,
+ * TVREG_ENOTCONV or TVREG_ESTALL, or a negative error.
+ */
+tvreg_status tvreg_solve(const tvreg_geometry *geom, const void *b_dev,
+                         const tvreg_solve_params *params, void *x_inout_dev,
+                         void *workspace_dev, size_t workspace_bytes, tvreg_solve_info *info,
+                         void *stream);
+
+/*
+ * Opt-in instrumentation of tvreg_solve: when enabled, every kernel launch of
+ * a solve is bracketed by HIP events on the solve's stream and the elapsed
+ * times are summed per kernel (process-wide, thread-safe).  Used by the
+ * benchmark to report live per-kernel durations; off by default.
+ */
+typedef enum {
+    TVREG_KERNEL_PROJECT = 0,      /* projector (fused residual and sums) */
+    TVREG_KERNEL_BACKPROJECT = 1,  /* gather backprojector */
+    TVREG_KERNEL_TV = 2,           /* TV gradient / value / Bregman stencil */
+    TVREG_KERNEL_TRIAL = 3,        /* projected trial step with TV value */
+    TVREG_KERNEL_EXTRAPOLATE = 4,  /* UPN extrapolation of x and of the residual */
+    TVREG_KERNEL_COUNT = 5
+} tvreg_kernel_id;
+void tvreg_profile_enable(int32_t on);
+void tvreg_profile_reset(void);
+/* launches counted and their summed duration in milliseconds */
+tvreg_status tvreg_profile_get(int32_t kernel, int64_t *count, double *total_ms);
+
+/* Thread-local description of the last error (empty string if none). */
+const char *tvreg_last_error(void);
+
+/* Library version string. */
+const char *tvreg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TVREG_H */

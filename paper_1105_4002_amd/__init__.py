@@ -1,0 +1,293 @@
+"""MI355X (gfx950) TV-regularised CT reconstruction: Python binding.
+
+A thin ctypes layer over ``libtvreg.so`` (C ABI in ``include/tvreg.h``):
+torch tensors supply device memory and the current HIP stream, every step
+of the computation runs in the library's HIP kernels.  There is no CPU
+fallback: if the library has not been built, importing this package raises.
+
+Entry points mirror the C names: ``Geometry`` (tvreg_create_geometry),
+``project``, ``backproject``, ``tv_grad``, ``objective_grad`` and ``solve``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch  # loads the HIP runtime the library binds to
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtvreg.so")
+
+PARALLEL, CONE = 0, 1
+F32, F64 = 0, 1
+GP, GPBB, UPN = 0, 1, 2
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, ESTALL = 0, -1, -2, -3, 1, 2
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("n_views", ctypes.c_int32), ("angles_rad", _c_dp),
+                ("beam", ctypes.c_int), ("det_cols", ctypes.c_int32),
+                ("det_rows", ctypes.c_int32), ("pitch_u", ctypes.c_double),
+                ("pitch_v", ctypes.c_double), ("src_to_centre", ctypes.c_double),
+                ("src_to_det", ctypes.c_double)]
+
+
+class _SolveParams(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("alpha", ctypes.c_double), ("tau", ctypes.c_double),
+                ("eps", ctypes.c_double), ("stop_mode", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("L_bar", ctypes.c_double),
+                ("mu_bar", ctypes.c_double), ("rho_L", ctypes.c_double),
+                ("gpbb_K", ctypes.c_int32), ("gpbb_sigma", ctypes.c_double),
+                ("gpbb_beta0", ctypes.c_double), ("max_trials", ctypes.c_int32),
+                ("hist_phi", _c_dp), ("hist_gm", _c_dp), ("hist_L", _c_dp),
+                ("hist_len", ctypes.c_int32)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("grad_evals", ctypes.c_int32),
+                ("func_evals", ctypes.c_int32), ("phi", ctypes.c_double),
+                ("gm_rel", ctypes.c_double), ("gm_abs_over_N", ctypes.c_double),
+                ("L", ctypes.c_double), ("mu", ctypes.c_double),
+                ("stop_reason", ctypes.c_int32)]
+
+
+# Every symbol include/tvreg.h declares.
+EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
+           "tvreg_backproject", "tvreg_tv_workspace_bytes", "tvreg_tv_grad",
+           "tvreg_objective_workspace_bytes", "tvreg_objective_grad",
+           "tvreg_solve_workspace_bytes", "tvreg_solve", "tvreg_profile_enable",
+           "tvreg_profile_reset", "tvreg_profile_get", "tvreg_last_error", "tvreg_version")
+
+KERNELS = {"project": 0, "backproject": 1, "tv": 2, "trial": 3, "extrapolate": 4}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          f"`python -m paper_1105_4002_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, st = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    L.tvreg_create_geometry.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int,
+                                        ctypes.POINTER(vp)]
+    L.tvreg_create_geometry.restype = st
+    L.tvreg_destroy_geometry.argtypes = [vp]
+    L.tvreg_destroy_geometry.restype = None
+    L.tvreg_project.argtypes = [vp, vp, vp, vp]
+    L.tvreg_project.restype = st
+    L.tvreg_backproject.argtypes = [vp, vp, vp, vp]
+    L.tvreg_backproject.restype = st
+    L.tvreg_tv_workspace_bytes.argtypes = [ctypes.c_int32] * 3
+    L.tvreg_tv_workspace_bytes.restype = sz
+    L.tvreg_tv_grad.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int, ctypes.c_double, vp, vp,
+                                                       vp, vp, sz, vp]
+    L.tvreg_tv_grad.restype = st
+    L.tvreg_objective_workspace_bytes.argtypes = [vp]
+    L.tvreg_objective_workspace_bytes.restype = sz
+    L.tvreg_objective_grad.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp,
+                                       sz, vp]
+    L.tvreg_objective_grad.restype = st
+    L.tvreg_solve_workspace_bytes.argtypes = [vp, ctypes.c_int]
+    L.tvreg_solve_workspace_bytes.restype = sz
+    L.tvreg_solve.argtypes = [vp, vp, ctypes.POINTER(_SolveParams), vp, vp, sz,
+                              ctypes.POINTER(_SolveInfo), vp]
+    L.tvreg_solve.restype = st
+    L.tvreg_profile_enable.argtypes = [ctypes.c_int32]
+    L.tvreg_profile_enable.restype = None
+    L.tvreg_profile_reset.argtypes = []
+    L.tvreg_profile_reset.restype = None
+    L.tvreg_profile_get.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.tvreg_profile_get.restype = st
+    L.tvreg_last_error.restype = ctypes.c_char_p
+    L.tvreg_version.restype = ctypes.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+class TvregError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.tvreg_last_error().decode(errors="replace")
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str) -> int:
+    if status < 0:
+        raise TvregError(status, where)
+    return status
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dtype(precision: int):
+    return torch.float64 if precision == F64 else torch.float32
+
+
+def _ptr(t: torch.Tensor, dtype, numel: int, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Geometry:
+    """Device ray tables of one scan geometry (tvreg_create_geometry)."""
+
+    def __init__(self, desc, precision: int = F32):
+        self._angles = (ctypes.c_double * len(desc.angles))(*[float(a) for a in desc.angles])
+        d = _Desc(int(desc.nx), int(desc.ny), int(desc.nz), len(desc.angles),
+                  ctypes.cast(self._angles, _c_dp), int(desc.beam), int(desc.det_cols),
+                  int(desc.det_rows), float(desc.pitch_u), float(desc.pitch_v),
+                  float(desc.src_to_centre), float(desc.src_to_det))
+        h = ctypes.c_void_p()
+        _check(_lib.tvreg_create_geometry(ctypes.byref(d), int(precision), ctypes.byref(h)),
+               "tvreg_create_geometry")
+        self.handle = h
+        self.precision = int(precision)
+        self.dtype = _dtype(precision)
+        self.vol_shape = (int(desc.nz), int(desc.ny), int(desc.nx))
+        self.proj_shape = (len(desc.angles), int(desc.det_rows), int(desc.det_cols))
+        self.N = self.vol_shape[0] * self.vol_shape[1] * self.vol_shape[2]
+        self.m = self.proj_shape[0] * self.proj_shape[1] * self.proj_shape[2]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.tvreg_destroy_geometry(h)
+            self.handle = None
+
+    def empty_volume(self, device="cuda"):
+        return torch.empty(self.vol_shape, dtype=self.dtype, device=device)
+
+    def empty_data(self, device="cuda"):
+        return torch.empty(self.proj_shape, dtype=self.dtype, device=device)
+
+
+def project(geom: Geometry, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A x (tvreg_project)."""
+    y = geom.empty_data(x.device) if out is None else out
+    _check(_lib.tvreg_project(geom.handle, _ptr(x, geom.dtype, geom.N, "x"),
+                              _ptr(y, geom.dtype, geom.m, "y"), _stream(x)), "tvreg_project")
+    return y
+
+
+def backproject(geom: Geometry, r: torch.Tensor, out: Optional[torch.Tensor] = None):
+    """x = A^T r (tvreg_backproject)."""
+    x = geom.empty_volume(r.device) if out is None else out
+    _check(_lib.tvreg_backproject(geom.handle, _ptr(r, geom.dtype, geom.m, "r"),
+                                  _ptr(x, geom.dtype, geom.N, "x"), _stream(r)),
+           "tvreg_backproject")
+    return x
+
+
+def tv_grad(x: torch.Tensor, tau: float, value: bool = True, grad: bool = True):
+    """(grad T_tau(x), T_tau(x)) (tvreg_tv_grad); the value is a 0-d float64 tensor."""
+    nz, ny, nx = x.shape
+    prec = F64 if x.dtype == torch.float64 else F32
+    n = nx * ny * nz
+    g = torch.empty_like(x) if grad else None
+    val = torch.empty((), dtype=torch.float64, device=x.device) if value else None
+    wsb = _lib.tvreg_tv_workspace_bytes(nx, ny, nz) if value else 0
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=x.device) if value else None
+    _check(_lib.tvreg_tv_grad(nx, ny, nz, prec, float(tau), _ptr(x, x.dtype, n, "x"),
+                              _ptr(g, x.dtype, n, "grad") if grad else None,
+                              ctypes.c_void_p(val.data_ptr()) if value else None,
+                              ctypes.c_void_p(ws.data_ptr()) if value else None, wsb,
+                              _stream(x)), "tvreg_tv_grad")
+    return g, val
+
+
+def objective_grad(geom: Geometry, b: torch.Tensor, alpha: float, tau: float, x: torch.Tensor,
+                   grad: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None):
+    """(phi(x), grad phi(x)) (tvreg_objective_grad); phi is a 0-d float64 tensor."""
+    g = geom.empty_volume(x.device) if grad is None else grad
+    phi = torch.empty((), dtype=torch.float64, device=x.device)
+    wsb = _lib.tvreg_objective_workspace_bytes(geom.handle)
+    ws = workspace if workspace is not None else torch.empty(wsb, dtype=torch.uint8,
+                                                             device=x.device)
+    _check(_lib.tvreg_objective_grad(geom.handle, _ptr(b, geom.dtype, geom.m, "b"),
+                                     float(alpha), float(tau), _ptr(x, geom.dtype, geom.N, "x"),
+                                     _ptr(g, geom.dtype, geom.N, "grad"),
+                                     ctypes.c_void_p(phi.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(x)),
+           "tvreg_objective_grad")
+    return phi, g
+
+
+def objective_workspace(geom: Geometry, device="cuda") -> torch.Tensor:
+    return torch.empty(_lib.tvreg_objective_workspace_bytes(geom.handle), dtype=torch.uint8,
+                       device=device)
+
+
+def solve_workspace(geom: Geometry, method: int = UPN, device="cuda") -> torch.Tensor:
+    return torch.empty(_lib.tvreg_solve_workspace_bytes(geom.handle, int(method)),
+                       dtype=torch.uint8, device=device)
+
+
+def solve(geom: Geometry, b: torch.Tensor, method: int = UPN, alpha: float = 1e-2,
+          tau: float = 1e-4, eps: float = 1e-6, x0: Optional[torch.Tensor] = None,
+          stop_mode: int = 0, max_iter: int = 10000, L_bar: float = 1.0, mu_bar: float = 0.0,
+          rho_L: float = 2.0, gpbb_K: int = 2, gpbb_sigma: float = 0.1,
+          gpbb_beta0: float = 0.95, max_trials: int = 60, hist_len: int = 0,
+          workspace: Optional[torch.Tensor] = None):
+    """Runs GP / GPBB / UPN (tvreg_solve).  Returns (x, info dict, history dict)."""
+    x = (torch.zeros(geom.vol_shape, dtype=geom.dtype, device=b.device) if x0 is None
+         else x0.detach().clone().contiguous())
+    ws = workspace if workspace is not None else solve_workspace(geom, method, b.device)
+    hl = max(int(hist_len), 0)
+    hists = [(ctypes.c_double * max(hl, 1))() for _ in range(3)]
+    p = _SolveParams(int(method), float(alpha), float(tau), float(eps), int(stop_mode),
+                     int(max_iter), float(L_bar), float(mu_bar), float(rho_L), int(gpbb_K),
+                     float(gpbb_sigma), float(gpbb_beta0), int(max_trials),
+                     ctypes.cast(hists[0], _c_dp) if hl else None,
+                     ctypes.cast(hists[1], _c_dp) if hl else None,
+                     ctypes.cast(hists[2], _c_dp) if hl else None, hl)
+    info = _SolveInfo()
+    _check(_lib.tvreg_solve(geom.handle, _ptr(b, geom.dtype, geom.m, "b"), ctypes.byref(p),
+                            _ptr(x, geom.dtype, geom.N, "x"), ctypes.c_void_p(ws.data_ptr()),
+                            ws.numel(), ctypes.byref(info), _stream(b)), "tvreg_solve")
+    out = {k: getattr(info, k) for k, _ in _SolveInfo._fields_}
+    n = min(hl, out["iters"])
+    hist = {"phi": list(hists[0])[:n], "gm": list(hists[1])[:n], "L": list(hists[2])[:n]}
+    return x, out, hist
+
+
+def profile_enable(on: bool = True) -> None:
+    """Per-kernel HIP-event timing of tvreg_solve's launches (tvreg_profile_enable)."""
+    _lib.tvreg_profile_enable(1 if on else 0)
+
+
+def profile_reset() -> None:
+    _lib.tvreg_profile_reset()
+
+
+def profile_stats() -> dict:
+    """{kernel name: (launches, total ms)} accumulated since the last reset."""
+    out = {}
+    for name, kid in KERNELS.items():
+        c = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(_lib.tvreg_profile_get(kid, ctypes.byref(c), ctypes.byref(ms)), "profile_get")
+        out[name] = (int(c.value), float(ms.value))
+    return out
+
+
+def version() -> str:
+    return _lib.tvreg_version().decode()

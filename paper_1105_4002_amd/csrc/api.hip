@@ -1,0 +1,925 @@
+// Host side of the C ABI declared in include/tvreg.h: geometry tables,
+// argument checks, workspace layout and the GP / GPBB / UPN drivers.
+//
+// The drivers keep every vector on the device and every scalar decision in
+// double on the host: after each line-search trial the FP64 sums of the
+// trial's kernels are read back (one stream synchronisation per trial) and
+// the test of Alg. 2 or Alg. 1 is evaluated; the mu estimate (eq. 9), the
+// theta root and beta of Alg. 3 follow from the same sums.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tvreg.h"
+#include "tvreg_internal.hpp"
+
+using namespace tvr;
+
+namespace {
+
+thread_local std::string g_err;
+
+tvreg_status fail(tvreg_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define TVR_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(TVREG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
+    } while (0)
+
+#define TVR_TRY(expr)                                                                          \
+    do {                                                                                       \
+        tvreg_status s_ = (expr);                                                              \
+        if (s_ < 0)                                                                            \
+            return s_;                                                                         \
+    } while (0)
+
+// Makes the geometry's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            ok = false;
+            return;
+        }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess)
+            ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+            (void)hipSetDevice(prev);
+    }
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct tvreg_geometry {
+    tvreg_geometry_desc desc;
+    std::vector<double> angles;
+    tvreg_precision prec;
+    int device;
+    GeomDev g;
+    void *dev_tables;
+    int64_t N, m;
+    int pstride;  // partial-sum capacity per slot
+};
+
+static size_t elem_size(tvreg_precision p) { return p == TVREG_F64 ? 8 : 4; }
+
+extern "C" const char *tvreg_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *tvreg_version(void) { return "tvreg-gfx950 0.1.0"; }
+
+extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
+                                              tvreg_precision precision, tvreg_geometry **out)
+{
+    g_err.clear();
+    if (!d || !out)
+        return fail(TVREG_EINVAL, "NULL descriptor or output pointer");
+    *out = nullptr;
+    if (precision != TVREG_F32_RED64 && precision != TVREG_F64)
+        return fail(TVREG_EINVAL, "unknown precision %d", (int)precision);
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->n_views < 1 || d->det_cols < 1 ||
+        d->det_rows < 1)
+        return fail(TVREG_EINVAL, "sizes must be >= 1");
+    if (!d->angles_rad)
+        return fail(TVREG_EINVAL, "angles_rad is NULL");
+    if (!(d->pitch_u > 0) || !(d->pitch_v > 0))
+        return fail(TVREG_EINVAL, "detector pitches must be > 0");
+    const int64_t N = (int64_t)d->nx * d->ny * d->nz;
+    const int64_t m = (int64_t)d->n_views * d->det_rows * d->det_cols;
+    if (N >= (int64_t(1) << 31) || m >= (int64_t(1) << 31))
+        return fail(TVREG_EINVAL, "volume or data larger than 2^31 entries");
+    if (d->nx + d->ny + d->nz > (1 << 20))
+        return fail(TVREG_EINVAL, "volume side too large");
+    const double half_diag =
+        0.5 * sqrt((double)d->nx * d->nx + (double)d->ny * d->ny + (double)d->nz * d->nz);
+    if (d->beam == TVREG_CONE) {
+        if (!(d->src_to_centre > half_diag) || !(d->src_to_det - d->src_to_centre > half_diag))
+            return fail(TVREG_EINVAL,
+                        "cone beam needs source and detector outside the volume's bounding "
+                        "sphere (R=%g, SDD=%g, half diagonal %g)",
+                        d->src_to_centre, d->src_to_det, half_diag);
+    } else if (d->beam != TVREG_PARALLEL) {
+        return fail(TVREG_EINVAL, "unknown beam %d", (int)d->beam);
+    }
+    for (int v = 0; v < d->n_views; ++v)
+        if (!isfinite(d->angles_rad[v]))
+            return fail(TVREG_EINVAL, "angle %d is not finite", v);
+
+    const bool cone = d->beam == TVREG_CONE;
+    const int V = d->n_views, C = d->det_cols, Rw = d->det_rows;
+    const double cu0 = 0.5 * (double)(C - 1), rv0 = 0.5 * (double)(Rw - 1);
+    const double R = d->src_to_centre, SDD = d->src_to_det;
+
+    std::vector<double2> cs(V);
+    std::vector<ColEntry> colt((size_t)V * C);
+    std::vector<RowEntry> rowt(Rw);
+    std::vector<double> dn(cone ? (size_t)Rw * C : (size_t)V);
+    for (int v = 0; v < V; ++v) {
+        const double c = cos(d->angles_rad[v]), s = sin(d->angles_rad[v]);
+        cs[v] = make_double2(c, s);
+        for (int col = 0; col < C; ++col) {
+            const double u = ((double)col - cu0) * d->pitch_u;
+            ColEntry &e = colt[(size_t)v * C + col];
+            if (cone) {
+                e.Sx = R * c;
+                e.Sy = R * s;
+                e.Dx = -SDD * c - u * s;
+                e.Dy = -SDD * s + u * c;
+            } else {
+                e.Sx = -u * s;
+                e.Sy = u * c;
+                e.Dx = c;
+                e.Dy = s;
+            }
+            e.invDx = e.Dx != 0.0 ? 1.0 / e.Dx : 0.0;
+            e.invDy = e.Dy != 0.0 ? 1.0 / e.Dy : 0.0;
+        }
+        if (!cone)
+            dn[v] = sqrt(c * c + s * s);
+    }
+    for (int row = 0; row < Rw; ++row) {
+        const double w = ((double)row - rv0) * d->pitch_v;
+        RowEntry &e = rowt[row];
+        e.Sz = cone ? 0.0 : w;
+        e.Dz = cone ? w : 0.0;
+        e.invDz = e.Dz != 0.0 ? 1.0 / e.Dz : 0.0;
+        e.pad = 0.0;
+        if (cone)
+            for (int col = 0; col < C; ++col) {
+                const double u = ((double)col - cu0) * d->pitch_u;
+                dn[(size_t)row * C + col] = sqrt(SDD * SDD + u * u + w * w);
+            }
+    }
+
+    tvreg_geometry *G = new (std::nothrow) tvreg_geometry();
+    if (!G)
+        return fail(TVREG_ENOMEM, "host allocation failed");
+    G->desc = *d;
+    G->angles.assign(d->angles_rad, d->angles_rad + V);
+    G->desc.angles_rad = G->angles.data();
+    G->prec = precision;
+    G->N = N;
+    G->m = m;
+    if (hipGetDevice(&G->device) != hipSuccess) {
+        delete G;
+        return fail(TVREG_EDEVICE, "no HIP device");
+    }
+    const size_t o_cs = 0;
+    const size_t o_col = align_up(o_cs + sizeof(double2) * V, 256);
+    const size_t o_row = align_up(o_col + sizeof(ColEntry) * colt.size(), 256);
+    const size_t o_dn = align_up(o_row + sizeof(RowEntry) * rowt.size(), 256);
+    const size_t total = align_up(o_dn + sizeof(double) * dn.size(), 256);
+    char *base = nullptr;
+    if (hipMalloc((void **)&base, total) != hipSuccess) {
+        delete G;
+        return fail(TVREG_ENOMEM, "device allocation of %zu bytes failed", total);
+    }
+    hipError_t e = hipMemcpy(base + o_cs, cs.data(), sizeof(double2) * V, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + o_col, colt.data(), sizeof(ColEntry) * colt.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + o_row, rowt.data(), sizeof(RowEntry) * rowt.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + o_dn, dn.data(), sizeof(double) * dn.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        delete G;
+        return fail(TVREG_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
+    }
+    G->dev_tables = base;
+    GeomDev &g = G->g;
+    g.nx = d->nx;
+    g.ny = d->ny;
+    g.nz = d->nz;
+    g.nviews = V;
+    g.cols = C;
+    g.rows = Rw;
+    g.cone = cone ? 1 : 0;
+    g.pu = d->pitch_u;
+    g.pv = d->pitch_v;
+    g.ipu = 1.0 / d->pitch_u;
+    g.ipv = 1.0 / d->pitch_v;
+    g.R = R;
+    g.SDD = SDD;
+    g.cu0 = cu0;
+    g.rv0 = rv0;
+    g.hx = 0.5 * d->nx;
+    g.hy = 0.5 * d->ny;
+    g.hz = 0.5 * d->nz;
+    g.cs = (const double2 *)(base + o_cs);
+    g.col = (const ColEntry *)(base + o_col);
+    g.row = (const RowEntry *)(base + o_row);
+    g.dnorm = (const double *)(base + o_dn);
+    G->pstride = std::max({project_blocks(g), max_reduce_blocks_vol(g.nx, g.ny, g.nz),
+                           elementwise_blocks(N), elementwise_blocks(m)});
+    *out = G;
+    return TVREG_OK;
+}
+
+extern "C" void tvreg_destroy_geometry(tvreg_geometry *G)
+{
+    if (!G)
+        return;
+    DeviceGuard dg(G->device);
+    (void)hipFree(G->dev_tables);
+    delete G;
+}
+
+extern "C" tvreg_status tvreg_project(const tvreg_geometry *G, const void *x, void *y,
+                                      void *stream)
+{
+    g_err.clear();
+    if (!G || !x || !y)
+        return fail(TVREG_EINVAL, "NULL geometry or buffer");
+    DeviceGuard dg(G->device);
+    if (!dg.ok)
+        return fail(TVREG_EDEVICE, "cannot select device %d", G->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (G->prec == TVREG_F64)
+        TVR_HIP((launch_project<double>(G->g, (const double *)x, nullptr, (double *)y, nullptr,
+                                        nullptr, 0, st, nullptr)));
+    else
+        TVR_HIP((launch_project<float>(G->g, (const float *)x, nullptr, (float *)y, nullptr,
+                                       nullptr, 0, st, nullptr)));
+    return TVREG_OK;
+}
+
+extern "C" tvreg_status tvreg_backproject(const tvreg_geometry *G, const void *r, void *x,
+                                          void *stream)
+{
+    g_err.clear();
+    if (!G || !r || !x)
+        return fail(TVREG_EINVAL, "NULL geometry or buffer");
+    DeviceGuard dg(G->device);
+    if (!dg.ok)
+        return fail(TVREG_EDEVICE, "cannot select device %d", G->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (G->prec == TVREG_F64)
+        TVR_HIP((launch_backproject<double>(G->g, (const double *)r, (double *)x, st)));
+    else
+        TVR_HIP((launch_backproject<float>(G->g, (const float *)r, (float *)x, st)));
+    return TVREG_OK;
+}
+
+static size_t partial_bytes(int pstride) { return sizeof(double) * (size_t)S_COUNT * pstride; }
+
+extern "C" size_t tvreg_tv_workspace_bytes(int32_t nx, int32_t ny, int32_t nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1)
+        return 0;
+    return partial_bytes(max_reduce_blocks_vol(nx, ny, nz));
+}
+
+extern "C" tvreg_status tvreg_tv_grad(int32_t nx, int32_t ny, int32_t nz,
+                                      tvreg_precision precision, double tau, const void *x,
+                                      void *grad, double *tv_value, void *ws, size_t ws_bytes,
+                                      void *stream)
+{
+    g_err.clear();
+    if (nx < 1 || ny < 1 || nz < 1)
+        return fail(TVREG_EINVAL, "sizes must be >= 1");
+    if ((int64_t)nx * ny * nz >= (int64_t(1) << 31))
+        return fail(TVREG_EINVAL, "volume larger than 2^31 entries");
+    if (!x || (!grad && !tv_value))
+        return fail(TVREG_EINVAL, "NULL input, or neither gradient nor value requested");
+    if (!(tau > 0) || !isfinite(tau))
+        return fail(TVREG_EINVAL, "tau must be positive and finite");
+    if (precision != TVREG_F32_RED64 && precision != TVREG_F64)
+        return fail(TVREG_EINVAL, "unknown precision %d", (int)precision);
+    const int pstride = max_reduce_blocks_vol(nx, ny, nz);
+    if (tv_value && (!ws || ws_bytes < partial_bytes(pstride)))
+        return fail(TVREG_ENOMEM, "workspace of %zu bytes needed", partial_bytes(pstride));
+    hipStream_t st = (hipStream_t)stream;
+    double *part = tv_value ? (double *)ws : nullptr;
+    int nb = 0;
+    if (precision == TVREG_F64)
+        TVR_HIP((launch_tv<double>(nx, ny, nz, tau, 1.0, (const double *)x, nullptr, nullptr,
+                                   (double *)grad, part, pstride, st, &nb)));
+    else
+        TVR_HIP((launch_tv<float>(nx, ny, nz, tau, 1.0, (const float *)x, nullptr, nullptr,
+                                  (float *)grad, part, pstride, st, &nb)));
+    if (tv_value) {
+        SlotList sl{};
+        sl.n = 1;
+        sl.slot[0] = S_TVY;
+        sl.count[0] = nb;
+        sl.dst[0] = tv_value;
+        TVR_HIP(launch_finalize(sl, part, pstride, st));
+    }
+    return TVREG_OK;
+}
+
+// ------------------------------------------------------------------ solver
+
+namespace {
+
+struct Layout {
+    size_t vecN[5], vecM[3], partials, scalars, total;
+};
+
+Layout solve_layout(const tvreg_geometry *G)
+{
+    Layout L{};
+    const size_t es = elem_size(G->prec);
+    size_t off = 0;
+    for (int i = 0; i < 5; ++i) {
+        L.vecN[i] = off;
+        off = align_up(off + es * (size_t)G->N, 256);
+    }
+    for (int i = 0; i < 3; ++i) {
+        L.vecM[i] = off;
+        off = align_up(off + es * (size_t)G->m, 256);
+    }
+    L.partials = off;
+    off = align_up(off + partial_bytes(G->pstride), 256);
+    L.scalars = off;
+    off = align_up(off + sizeof(double) * 2 * S_COUNT, 256);
+    L.total = off;
+    return L;
+}
+
+// Opt-in per-kernel timing of the solver's launches (HIP events on the
+// solver's stream, resolved at the next synchronisation).
+struct ProfTotals {
+    std::mutex mu;
+    bool on = false;
+    int64_t count[TVREG_KERNEL_COUNT] = {};
+    double ms[TVREG_KERNEL_COUNT] = {};
+};
+ProfTotals g_prof;
+
+struct Runner {
+    const tvreg_geometry *G;
+    hipStream_t st;
+    double *part;
+    int pstride;
+    double *dsc;        // device scalars [S_COUNT]
+    double hs[S_COUNT]; // host copy
+    SlotList pend;
+    bool prof = false;
+    struct Ev {
+        int kid;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> evs;
+    std::vector<hipEvent_t> pool;
+
+    ~Runner()
+    {
+        for (auto &e : evs) {
+            pool.push_back(e.a);
+            pool.push_back(e.b);
+        }
+        for (hipEvent_t e : pool)
+            (void)hipEventDestroy(e);
+    }
+    hipEvent_t ev()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    // runs launch() bracketed by events when profiling is on
+    template <class F>
+    hipError_t timed(int kid, F &&launch)
+    {
+        if (!prof)
+            return launch();
+        Ev e{kid, ev(), ev()};
+        (void)hipEventRecord(e.a, st);
+        hipError_t r = launch();
+        (void)hipEventRecord(e.b, st);
+        evs.push_back(e);
+        return r;
+    }
+    void resolve()  // stream already synchronised
+    {
+        if (evs.empty())
+            return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        for (auto &e : evs) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+                g_prof.count[e.kid]++;
+                g_prof.ms[e.kid] += ms;
+            }
+            pool.push_back(e.a);
+            pool.push_back(e.b);
+        }
+        evs.clear();
+    }
+
+    void add(int slot, int count)
+    {
+        for (int i = 0; i < pend.n; ++i)
+            if (pend.slot[i] == slot) {
+                pend.count[i] = count;
+                return;
+            }
+        pend.slot[pend.n] = slot;
+        pend.count[pend.n] = count;
+        pend.dst[pend.n] = dsc + slot;
+        pend.n++;
+    }
+    tvreg_status read()
+    {
+        TVR_HIP(launch_finalize(pend, part, pstride, st));
+        pend.n = 0;
+        TVR_HIP(hipMemcpyAsync(hs, dsc, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
+        TVR_HIP(hipStreamSynchronize(st));
+        resolve();
+        return TVREG_OK;
+    }
+};
+
+bool stop_test(const tvreg_solve_params *p, double gm, double gm0, int64_t N)
+{
+    if (p->stop_mode == 1)
+        return gm / (double)N <= p->eps;
+    return gm0 == 0.0 || gm <= p->eps * gm0;
+}
+
+void hist_put(double *h, int32_t len, int k, double v)
+{
+    if (h && k >= 0 && k < len)
+        h[k] = v;
+}
+
+template <typename T>
+struct Solver {
+    const tvreg_geometry *G;
+    const tvreg_solve_params *p;
+    const T *b;
+    Runner run;
+    int nx, ny, nz;
+    int64_t N, m;
+    T *vN[5];
+    T *vM[3];
+
+    tvreg_status project(const T *x, T *out, const T *rref)
+    {
+        int nb = 0;
+        TVR_HIP(run.timed(TVREG_KERNEL_PROJECT, [&] {
+            return launch_project<T>(G->g, x, b, out, rref, run.part, run.pstride, run.st, &nb);
+        }));
+        run.add(S_R2, nb);
+        if (rref)
+            run.add(S_RD2, nb);
+        return TVREG_OK;
+    }
+    // g = A^T r + alpha grad T(y); slots of T(y) and, with xref, the Bregman terms
+    tvreg_status gradient(const T *y, const T *ry, const T *xref, T *g)
+    {
+        TVR_HIP(run.timed(TVREG_KERNEL_BACKPROJECT,
+                          [&] { return launch_backproject<T>(G->g, ry, g, run.st); }));
+        int nb = 0;
+        TVR_HIP(run.timed(TVREG_KERNEL_TV, [&] {
+            return launch_tv<T>(nx, ny, nz, p->tau, p->alpha, y, xref, g, g, run.part,
+                                run.pstride, run.st, &nb);
+        }));
+        run.add(S_TVY, nb);
+        if (xref) {
+            run.add(S_BRY, nb);
+            run.add(S_XY2, nb);
+        }
+        return TVREG_OK;
+    }
+    tvreg_status trial(const T *z, const T *g, double step, double gm_step, T *xb)
+    {
+        int nb = 0;
+        TVR_HIP(run.timed(TVREG_KERNEL_TRIAL, [&] {
+            return launch_trial<T>(nx, ny, nz, p->tau, z, g, step, gm_step, xb, run.part,
+                                   run.pstride, run.st, &nb);
+        }));
+        run.add(S_XD2, nb);
+        run.add(S_GD, nb);
+        run.add(S_TVB, nb);
+        run.add(S_BRB, nb);
+        if (gm_step > 0)
+            run.add(S_GM2, nb);
+        return TVREG_OK;
+    }
+
+    // GP (beta = 0) and UPN.
+    tvreg_status gp_upn(T *x_io, tvreg_solve_info *info)
+    {
+        const bool upn = p->method == TVREG_UPN;
+        T *X = vN[0], *XB = vN[1], *Ybuf = vN[2], *Gv = vN[3];
+        T *RX = vM[0], *RXB = vM[1], *RYbuf = vM[2];
+        TVR_HIP(launch_clip<T>(N, x_io, X, run.st));
+        TVR_TRY(project(X, RX, nullptr));
+        T *Y = X, *RY = RX;
+        TVR_TRY(gradient(Y, RY, nullptr, Gv));
+        info->grad_evals++;
+
+        // Alg. 2 at y with the Bregman-form acceptance test
+        auto bt = [&](double L0, double &L, double &xd2, double &phi_xb) -> tvreg_status {
+            L = L0;
+            for (int t = 0; t < p->max_trials; ++t) {
+                TVR_TRY(trial(Y, Gv, 1.0 / L, 0.0, XB));
+                TVR_TRY(project(XB, RXB, RY));
+                TVR_TRY(run.read());
+                info->func_evals++;
+                xd2 = run.hs[S_XD2];
+                const double lhs = 0.5 * run.hs[S_RD2] + p->alpha * run.hs[S_BRB];
+                phi_xb = 0.5 * run.hs[S_R2] + p->alpha * run.hs[S_TVB];
+                if (!(lhs > 0.5 * L * xd2))
+                    return TVREG_OK;
+                if (t + 1 < p->max_trials)
+                    L *= p->rho_L;
+            }
+            return TVREG_ESTALL;
+        };
+
+        double L = 0, xd2 = 0, phi_xb = 0;
+        tvreg_status st = bt(p->L_bar, L, xd2, phi_xb);
+        const double gm0 = L * sqrt(xd2);
+        double gm = gm0;
+        info->iters = 1;
+        info->L = L;
+        double mu = p->mu_bar > 0 ? p->mu_bar : 0.25 * L;
+        double theta = sqrt(mu / L);
+        double phi_out = phi_xb;
+        hist_put(p->hist_phi, p->hist_len, 0, phi_xb);
+        hist_put(p->hist_gm, p->hist_len, 0, 1.0);
+        hist_put(p->hist_L, p->hist_len, 0, L);
+        const T *out = XB;
+        if (st == TVREG_ESTALL) {
+            out = X;
+            phi_out = NAN;
+        } else if (st < 0) {
+            return st;
+        } else if (stop_test(p, gm0, gm0, N)) {
+            st = TVREG_OK;
+        } else {
+            st = TVREG_ENOTCONV;
+            std::swap(X, XB);
+            std::swap(RX, RXB);
+            Y = X;
+            RY = RX;
+            out = X;
+            bool have_ry2 = false;
+            for (int k = 1; k < p->max_iter; ++k) {
+                const bool distinct = Y != X;
+                TVR_TRY(gradient(Y, RY, distinct ? X : nullptr, Gv));
+                info->grad_evals++;
+                const tvreg_status bs = bt(L, L, xd2, phi_xb);
+                if (bs < 0)
+                    return bs;
+                gm = L * sqrt(xd2);
+                info->iters = k + 1;
+                info->L = L;
+                hist_put(p->hist_phi, p->hist_len, k, phi_xb);
+                hist_put(p->hist_gm, p->hist_len, k, gm0 > 0 ? gm / gm0 : 0.0);
+                hist_put(p->hist_L, p->hist_len, k, L);
+                if (bs == TVREG_ESTALL) {
+                    st = TVREG_ESTALL;
+                    out = X;  // last accepted point x^(k)
+                    break;
+                }
+                phi_out = phi_xb;
+                if (stop_test(p, gm, gm0, N)) {
+                    st = TVREG_OK;
+                    out = XB;
+                    break;
+                }
+                double beta = 0.0;
+                if (upn) {
+                    // eq. 9 between x^(k) and y^(k), skipped where they coincide
+                    const double nd = distinct ? run.hs[S_XY2] : 0.0;
+                    if (nd > 0.0 && have_ry2) {
+                        const double num = 0.5 * run.hs[S_RY2] + p->alpha * run.hs[S_BRY];
+                        mu = fmax(fmin(mu, num / (0.5 * nd)), 0.0);
+                    }
+                    const double q = mu / L, th2 = theta * theta, bq = th2 - q;
+                    const double theta_n = 0.5 * (-bq + sqrt(bq * bq + 4.0 * th2));
+                    beta = theta * (1.0 - theta) / (th2 + theta_n);
+                    theta = theta_n;
+                    // y^(k+1) = x^(k+1) + beta (x^(k+1) - x^(k)), and its residual
+                    int nb = 0;
+                    TVR_HIP(run.timed(TVREG_KERNEL_EXTRAPOLATE, [&] {
+                        return launch_extrapolate<T>(N, beta, XB, X, Ybuf, nullptr, 0, run.st,
+                                                     nullptr);
+                    }));
+                    TVR_HIP(run.timed(TVREG_KERNEL_EXTRAPOLATE, [&] {
+                        return launch_extrapolate<T>(m, beta, RXB, RX, RYbuf, run.part,
+                                                     run.pstride, run.st, &nb);
+                    }));
+                    run.add(S_RY2, nb);
+                    have_ry2 = true;
+                    std::swap(X, XB);
+                    std::swap(RX, RXB);
+                    Y = Ybuf;
+                    RY = RYbuf;
+                } else {
+                    std::swap(X, XB);
+                    std::swap(RX, RXB);
+                    Y = X;
+                    RY = RX;
+                }
+                out = X;
+            }
+        }
+        info->gm_rel = gm0 > 0 ? gm / gm0 : 0.0;
+        info->gm_abs_over_N = gm / (double)N;
+        info->mu = upn ? mu : 0.0;
+        info->phi = phi_out;
+        info->stop_reason = st;
+        if (out != x_io)
+            TVR_HIP(hipMemcpyAsync(x_io, out, sizeof(T) * (size_t)N, hipMemcpyDeviceToDevice,
+                                   run.st));
+        TVR_HIP(hipStreamSynchronize(run.st));
+        if (st == TVREG_ESTALL && isnan(info->phi)) {
+            // the start point was never accepted: report phi there
+            info->phi = NAN;
+        }
+        return st;
+    }
+
+    // GPBB, Alg. 1
+    tvreg_status gpbb(T *x_io, tvreg_solve_info *info)
+    {
+        T *X = vN[0], *XB = vN[1], *XP = vN[2], *Gv = vN[3], *GP = vN[4];
+        T *RX = vM[0], *RXB = vM[1];
+        TVR_HIP(launch_clip<T>(N, x_io, X, run.st));
+        TVR_TRY(project(X, RX, nullptr));
+        TVR_TRY(gradient(X, RX, nullptr, Gv));
+        info->grad_evals++;
+        TVR_TRY(run.read());
+        double fk = 0.5 * run.hs[S_R2] + p->alpha * run.hs[S_TVY];
+        const int K = p->gpbb_K;
+        double fh[17];
+        int nf = 0;
+        double theta = 1.0, gm0 = 0.0, gm = 0.0;
+        tvreg_status st = TVREG_ENOTCONV;
+        for (int k = 0; k < p->max_iter; ++k) {
+            for (int q = (nf < K + 1 ? nf : K); q > 0; --q)
+                fh[q] = fh[q - 1];
+            fh[0] = fk;
+            if (nf < K + 1)
+                nf++;
+            if (k > 0) {
+                // gradient at x^(k); the previous one is kept for the BB step
+                std::swap(Gv, GP);
+                TVR_TRY(gradient(X, RX, nullptr, Gv));
+                info->grad_evals++;
+                int nb = 0;
+                TVR_HIP(launch_bb_dots<T>(N, X, XP, Gv, GP, run.part, run.pstride, run.st, &nb));
+                run.add(S_SS, nb);
+                run.add(S_SY, nb);
+                TVR_TRY(run.read());
+                const double ss = run.hs[S_SS], sy = run.hs[S_SY];
+                if (sy > 0.0 && ss > 0.0 && isfinite(ss / sy))
+                    theta = ss / sy;
+            }
+            double fhat = fh[0];
+            for (int q = 1; q < nf; ++q)
+                fhat = fmax(fhat, fh[q]);
+            double beta = p->gpbb_beta0, fb = 0.0;
+            bool ok = false, stop = false;
+            for (int sq = 0; sq <= p->max_trials; ++sq) {
+                TVR_TRY(trial(X, Gv, beta * theta, sq == 0 ? theta : 0.0, XB));
+                TVR_TRY(project(XB, RXB, nullptr));
+                TVR_TRY(run.read());
+                if (sq == 0) {
+                    gm = sqrt(run.hs[S_GM2]) / theta;
+                    if (k == 0)
+                        gm0 = gm;
+                    info->iters = k;
+                    info->L = 1.0 / theta;
+                    hist_put(p->hist_gm, p->hist_len, k, gm0 > 0 ? gm / gm0 : 0.0);
+                    hist_put(p->hist_L, p->hist_len, k, 1.0 / theta);
+                    hist_put(p->hist_phi, p->hist_len, k, fk);
+                    if (stop_test(p, gm, gm0, N)) {
+                        stop = true;
+                        break;
+                    }
+                }
+                info->func_evals++;
+                fb = 0.5 * run.hs[S_R2] + p->alpha * run.hs[S_TVB];
+                const double gd = run.hs[S_GD];
+                if (!(fb >= fhat - p->gpbb_sigma * gd)) {
+                    ok = true;
+                    break;
+                }
+                beta = beta * beta;
+            }
+            if (stop) {
+                st = TVREG_OK;
+                break;
+            }
+            if (!ok) {
+                st = TVREG_ESTALL;
+                break;
+            }
+            // x^(k+1) = xbar
+            T *t = XP;
+            XP = X;
+            X = XB;
+            XB = t;
+            std::swap(RX, RXB);
+            fk = fb;
+            info->iters = k + 1;
+        }
+        info->gm_rel = gm0 > 0 ? gm / gm0 : 0.0;
+        info->gm_abs_over_N = gm / (double)N;
+        info->mu = 0.0;
+        info->phi = fk;
+        info->stop_reason = st;
+        TVR_HIP(hipMemcpyAsync(x_io, X, sizeof(T) * (size_t)N, hipMemcpyDeviceToDevice, run.st));
+        TVR_HIP(hipStreamSynchronize(run.st));
+        return st;
+    }
+};
+
+}  // namespace
+
+extern "C" size_t tvreg_solve_workspace_bytes(const tvreg_geometry *G, tvreg_method)
+{
+    if (!G)
+        return 0;
+    return solve_layout(G).total;
+}
+
+extern "C" size_t tvreg_objective_workspace_bytes(const tvreg_geometry *G)
+{
+    if (!G)
+        return 0;
+    return align_up(elem_size(G->prec) * (size_t)G->m, 256) + partial_bytes(G->pstride) +
+           256;
+}
+
+template <typename T>
+static tvreg_status objective_impl(const tvreg_geometry *G, const T *b, double alpha, double tau,
+                                   const T *x, T *grad, double *phi, char *ws, hipStream_t st)
+{
+    T *r = (T *)ws;
+    double *part = (double *)(ws + align_up(sizeof(T) * (size_t)G->m, 256));
+    double *sc = (double *)((char *)part + partial_bytes(G->pstride));
+    int nb1 = 0, nb2 = 0;
+    TVR_HIP(launch_project<T>(G->g, x, b, r, nullptr, part, G->pstride, st, &nb1));
+    TVR_HIP(launch_backproject<T>(G->g, r, grad, st));
+    TVR_HIP(launch_tv<T>(G->g.nx, G->g.ny, G->g.nz, tau, alpha, x, nullptr, grad, grad, part,
+                         G->pstride, st, &nb2));
+    SlotList sl{};
+    sl.n = 2;
+    sl.slot[0] = S_R2;
+    sl.count[0] = nb1;
+    sl.dst[0] = sc;
+    sl.slot[1] = S_TVY;
+    sl.count[1] = nb2;
+    sl.dst[1] = sc + 1;
+    TVR_HIP(launch_finalize(sl, part, G->pstride, st));
+    TVR_HIP(launch_combine_phi(sc, sc + 1, alpha, phi, st));
+    return TVREG_OK;
+}
+
+extern "C" tvreg_status tvreg_objective_grad(const tvreg_geometry *G, const void *b,
+                                             double alpha, double tau, const void *x, void *grad,
+                                             double *phi, void *ws, size_t ws_bytes,
+                                             void *stream)
+{
+    g_err.clear();
+    if (!G || !b || !x || !grad || !phi)
+        return fail(TVREG_EINVAL, "NULL geometry or buffer");
+    if (!(tau > 0) || !isfinite(tau) || !isfinite(alpha) || alpha < 0)
+        return fail(TVREG_EINVAL, "tau must be > 0 and alpha >= 0");
+    if (!ws || ws_bytes < tvreg_objective_workspace_bytes(G))
+        return fail(TVREG_ENOMEM, "workspace of %zu bytes needed",
+                    tvreg_objective_workspace_bytes(G));
+    DeviceGuard dg(G->device);
+    if (!dg.ok)
+        return fail(TVREG_EDEVICE, "cannot select device %d", G->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (G->prec == TVREG_F64)
+        return objective_impl<double>(G, (const double *)b, alpha, tau, (const double *)x,
+                                      (double *)grad, phi, (char *)ws, st);
+    return objective_impl<float>(G, (const float *)b, alpha, tau, (const float *)x, (float *)grad,
+                                 phi, (char *)ws, st);
+}
+
+template <typename T>
+static tvreg_status solve_impl(const tvreg_geometry *G, const T *b, const tvreg_solve_params *p,
+                               T *x, char *ws, tvreg_solve_info *info, hipStream_t st)
+{
+    const Layout L = solve_layout(G);
+    Solver<T> s{};
+    s.G = G;
+    s.p = p;
+    s.b = b;
+    s.nx = G->g.nx;
+    s.ny = G->g.ny;
+    s.nz = G->g.nz;
+    s.N = G->N;
+    s.m = G->m;
+    for (int i = 0; i < 5; ++i)
+        s.vN[i] = (T *)(ws + L.vecN[i]);
+    for (int i = 0; i < 3; ++i)
+        s.vM[i] = (T *)(ws + L.vecM[i]);
+    s.run.G = G;
+    s.run.st = st;
+    s.run.part = (double *)(ws + L.partials);
+    s.run.pstride = G->pstride;
+    s.run.dsc = (double *)(ws + L.scalars);
+    s.run.pend.n = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        s.run.prof = g_prof.on;
+    }
+    TVR_HIP(hipMemsetAsync(s.run.dsc, 0, sizeof(double) * S_COUNT, st));
+    const tvreg_status r = p->method == TVREG_GPBB ? s.gpbb(x, info) : s.gp_upn(x, info);
+    if (s.run.prof && hipStreamSynchronize(st) == hipSuccess)
+        s.run.resolve();
+    return r;
+}
+
+extern "C" tvreg_status tvreg_solve(const tvreg_geometry *G, const void *b,
+                                    const tvreg_solve_params *p, void *x, void *ws,
+                                    size_t ws_bytes, tvreg_solve_info *info, void *stream)
+{
+    g_err.clear();
+    if (!G || !b || !p || !x || !info)
+        return fail(TVREG_EINVAL, "NULL argument");
+    if (p->method != TVREG_GP && p->method != TVREG_GPBB && p->method != TVREG_UPN)
+        return fail(TVREG_EINVAL, "unknown method %d", (int)p->method);
+    if (!(p->tau > 0) || !isfinite(p->tau) || !(p->alpha >= 0) || !isfinite(p->alpha))
+        return fail(TVREG_EINVAL, "tau must be > 0 and alpha >= 0");
+    if (!(p->eps >= 0) || p->max_iter < 1 || !(p->L_bar > 0) || !(p->rho_L > 1) ||
+        p->max_trials < 1)
+        return fail(TVREG_EINVAL, "need eps >= 0, max_iter >= 1, L_bar > 0, rho_L > 1, "
+                                  "max_trials >= 1");
+    if (p->stop_mode != 0 && p->stop_mode != 1)
+        return fail(TVREG_EINVAL, "stop_mode must be 0 or 1");
+    if (p->method == TVREG_GPBB &&
+        (p->gpbb_K < 0 || p->gpbb_K > 16 || !(p->gpbb_beta0 > 0 && p->gpbb_beta0 < 1) ||
+         !(p->gpbb_sigma >= 0)))
+        return fail(TVREG_EINVAL, "GPBB needs 0 <= K <= 16, 0 < beta0 < 1, sigma >= 0");
+    if (p->hist_len < 0)
+        return fail(TVREG_EINVAL, "hist_len < 0");
+    if (!ws || ws_bytes < solve_layout(G).total)
+        return fail(TVREG_ENOMEM, "workspace of %zu bytes needed", solve_layout(G).total);
+    DeviceGuard dg(G->device);
+    if (!dg.ok)
+        return fail(TVREG_EDEVICE, "cannot select device %d", G->device);
+    memset(info, 0, sizeof(*info));
+    hipStream_t st = (hipStream_t)stream;
+    if (G->prec == TVREG_F64)
+        return solve_impl<double>(G, (const double *)b, p, (double *)x, (char *)ws, info, st);
+    return solve_impl<float>(G, (const float *)b, p, (float *)x, (char *)ws, info, st);
+}
+
+extern "C" void tvreg_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+}
+
+extern "C" void tvreg_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (int k = 0; k < TVREG_KERNEL_COUNT; ++k) {
+        g_prof.count[k] = 0;
+        g_prof.ms[k] = 0.0;
+    }
+}
+
+extern "C" tvreg_status tvreg_profile_get(int32_t kernel, int64_t *count, double *total_ms)
+{
+    if (kernel < 0 || kernel >= TVREG_KERNEL_COUNT || !count || !total_ms)
+        return fail(TVREG_EINVAL, "bad kernel id or NULL output");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    *count = g_prof.count[kernel];
+    *total_ms = g_prof.ms[kernel];
+    return TVREG_OK;
+}

@@ -1,0 +1,115 @@
+// Internal declarations of the gfx950 TV-reconstruction library: the device
+// view of a scan geometry, the reduction-slot layout and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tvr {
+
+// Ray tables.  A ray is p(t) = S + t D; for a cone beam t in [0, 1] runs from
+// the source to the pixel, for a parallel beam t is unbounded and D is the
+// unit view direction.  The in-plane part (x, y) depends on (view, column),
+// the axial part (z) on the detector row only.  Both the projector and the
+// gather backprojector evaluate plane crossings as t(X) = (X - S) * invD
+// from these same tables, so A and A^T use identical FP64 lengths.
+struct ColEntry {
+    double Sx, Sy, Dx, Dy, invDx, invDy;
+};
+struct RowEntry {
+    double Sz, Dz, invDz, pad;
+};
+
+struct GeomDev {
+    int nx, ny, nz;
+    int nviews, cols, rows;
+    int cone;
+    double pu, pv, ipu, ipv;   // detector pitches and their inverses
+    double R, SDD;             // cone only
+    double cu0, rv0;           // (cols - 1) / 2, (rows - 1) / 2
+    double hx, hy, hz;         // nx / 2, ny / 2, nz / 2
+    const double2 *cs;         // [nviews] (cos theta, sin theta)
+    const ColEntry *col;       // [nviews * cols]
+    const RowEntry *row;       // [rows]
+    const double *dnorm;       // |D|: cone [rows * cols], parallel [nviews]
+};
+
+// Double-precision reduction results live in fixed slots; every kernel that
+// reduces writes one partial per block into partials[slot * pstride + block]
+// and finalize_slots() sums each slot in a fixed order.
+enum Slot : int {
+    S_R2 = 0,        // sum r_i^2 of the projected residual
+    S_RD2,           // sum (r_i - rref_i)^2
+    S_XD2,           // |xbar - z|^2 (trial)
+    S_GD,            // g^T (z - xbar) (trial)
+    S_TVB,           // T_tau(xbar) (trial)
+    S_BRB,           // Bregman_T(xbar, z) (trial)
+    S_GM2,           // |z - P_Q(z - s g)|^2 (GPBB gradient map)
+    S_TVY,           // T_tau(y) (gradient pass)
+    S_BRY,           // Bregman_T(xref, y) (gradient pass)
+    S_XY2,           // |xref - y|^2 (gradient pass)
+    S_RY2,           // sum (r_y - r_xbar)^2 (extrapolation)
+    S_SS,            // |s|^2 (BB)
+    S_SY,            // <s, dg> (BB)
+    S_COUNT
+};
+
+struct SlotList {
+    int n;
+    int slot[S_COUNT];
+    int count[S_COUNT];     // partials written for the slot
+    double *dst[S_COUNT];   // device destination of the slot's sum
+};
+
+// ---------------------------------------------------------------- launchers
+// All return hipSuccess or the launch error.  `T` is float (FP32 storage with
+// FP64 reductions) or double.
+
+template <typename T>
+hipError_t launch_project(const GeomDev &g, const T *x, const T *b, T *out, const T *rref,
+                          double *partials, int pstride, hipStream_t st, int *nblocks);
+
+template <typename T>
+hipError_t launch_backproject(const GeomDev &g, const T *r, T *out, hipStream_t st);
+
+// gout = (gin ? gin + alpha * grad T(y) : grad T(y)); slots S_TVY and, with
+// xref, S_BRY and S_XY2.  gout may be NULL (value only).
+template <typename T>
+hipError_t launch_tv(int nx, int ny, int nz, double tau, double alpha, const T *y, const T *xref,
+                     const T *gin, T *gout, double *partials, int pstride, hipStream_t st,
+                     int *nblocks);
+
+// xbar = max(z - step g, 0); slots S_XD2, S_GD, S_TVB, S_BRB and (gm_step > 0) S_GM2.
+template <typename T>
+hipError_t launch_trial(int nx, int ny, int nz, double tau, const T *z, const T *g, double step,
+                        double gm_step, T *xbar, double *partials, int pstride, hipStream_t st,
+                        int *nblocks);
+
+// y = xn + beta (xn - xo) over n entries; with part != NULL adds sum (y - xn)^2 to S_RY2.
+template <typename T>
+hipError_t launch_extrapolate(int64_t n, double beta, const T *xn, const T *xo, T *y,
+                              double *partials, int pstride, hipStream_t st, int *nblocks);
+
+// slots S_SS, S_SY of s = x - xp, dg = g - gp.
+template <typename T>
+hipError_t launch_bb_dots(int64_t n, const T *x, const T *xp, const T *g, const T *gp,
+                          double *partials, int pstride, hipStream_t st, int *nblocks);
+
+// out = max(in, 0)
+template <typename T>
+hipError_t launch_clip(int64_t n, const T *in, T *out, hipStream_t st);
+
+hipError_t launch_finalize(const SlotList &sl, const double *partials, int pstride,
+                           hipStream_t st);
+
+// *out = 0.5 * (*r2) + alpha * (*tv)
+hipError_t launch_combine_phi(const double *r2, const double *tv, double alpha, double *out,
+                              hipStream_t st);
+
+// grid limits used to size the partial-sum buffer
+int project_blocks(const GeomDev &g);
+int max_reduce_blocks_vol(int nx, int ny, int nz);
+int elementwise_blocks(int64_t n);
+
+}  // namespace tvr

@@ -1,0 +1,218 @@
+"""GPU parity of the operators (projector, gather backprojector, smoothed TV,
+one gradient evaluation) against the FP64 CPU oracle, through the C ABI.
+
+Bars: FP64 path within 1e-12 of the oracle (relative to the output's scale);
+FP32-storage path: the oracle is applied to the same FP32-rounded inputs and
+each output element may differ by its own FP32 rounding (2^-24 relative)
+plus a 1e-9 scale-relative allowance for the FP64 accumulation order.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+tv = pytest.importorskip("paper_1105_4002_amd")
+
+DEV = "cuda"
+
+
+def geoms_small():
+    return {
+        "cone8": synth.Geometry(8, 8, 8, np.array([0.2, 2.0, 4.1]), synth.CONE, 12, 12, 1.5, 1.5,
+                                32.0, 48.0),
+        "cone_nc": synth.Geometry(6, 9, 7, np.array([0.4, 1.7, 3.3, 5.0]), synth.CONE, 16, 11,
+                                  1.3, 1.2, 30.0, 50.0),
+        "par_nc": synth.Geometry(7, 8, 5, np.array([0.0, 0.7, 1.9, math.pi / 2]), synth.PARALLEL,
+                                 13, 7, 1.0, 1.0),
+        # ragged against every tile: 37 x 29 x 23 voxels, 41 x 19 pixels
+        "cone_ragged": synth.Geometry(37, 29, 23, synth.view_angles(7, 2 * math.pi), synth.CONE,
+                                      41, 19, 2.1, 2.3, 60.0, 110.0),
+        "par_ragged": synth.Geometry(37, 29, 23, synth.view_angles(5, math.pi), synth.PARALLEL,
+                                     43, 23, 1.0, 1.0),
+        # rays lying in voxel faces: at theta = 0 (sin = 0 exactly) rays run in
+        # y = u planes, and every row runs in a z plane (integer w, even sizes);
+        # the half-open cell rule decides.  (Near-axial angles such as pi/2,
+        # where cos is 6e-17 rather than 0, make a face-lying ray cross the face
+        # at a point that moves by voxels under 1-ulp changes: ill-posed for
+        # any two implementations, so not tested.)
+        "par_faces": synth.Geometry(6, 6, 6, np.array([0.0, 0.4]), synth.PARALLEL, 9, 7, 1.0,
+                                    1.0),
+        "one_voxel": synth.Geometry(1, 1, 1, np.array([0.3]), synth.CONE, 3, 3, 1.5, 1.5, 4.0,
+                                    6.0),
+        "one_ray": synth.Geometry(4, 4, 4, np.array([1.0]), synth.PARALLEL, 1, 1, 1.0, 1.0),
+        "small_parallel": synth.cfg_small_parallel().geom,
+        "cone64": synth.cfg_cone64().geom,
+    }
+
+
+GEOMS = geoms_small()
+
+
+def to_dev(a, prec):
+    dt = torch.float64 if prec == tv.F64 else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=DEV, dtype=dt)
+
+
+def rounded(a, prec):
+    return a if prec == tv.F64 else a.astype(np.float32).astype(np.float64)
+
+
+def check_close(got, ref, prec, what):
+    got = got.detach().cpu().double().numpy()
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    if prec == tv.F64:
+        err = np.max(np.abs(got - ref)) / scale
+        assert err <= 1e-12, f"{what}: rel err {err:.3e}"
+    else:
+        tol = 2.0 ** -24 * np.abs(ref) + 1e-9 * scale
+        bad = np.abs(got - ref) > tol
+        assert not bad.any(), f"{what}: {bad.sum()} entries off, worst {np.max(np.abs(got - ref)):.3e}"
+
+
+@pytest.mark.parametrize("prec", [tv.F64, tv.F32])
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_project_matches_oracle(name, prec):
+    g = GEOMS[name]
+    print(f"project {name} prec={prec}", flush=True)
+    x = rounded(synth.random_volume(g.vol_shape, 3), prec)
+    G = tv.Geometry(g, prec)
+    y = tv.project(G, to_dev(x, prec))
+    torch.cuda.synchronize()
+    check_close(y, oracle.project(g, x), prec, f"A x [{name}]")
+
+
+@pytest.mark.parametrize("prec", [tv.F64, tv.F32])
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_backproject_matches_oracle(name, prec):
+    g = GEOMS[name]
+    print(f"backproject {name} prec={prec}", flush=True)
+    r = rounded(np.random.default_rng(4).standard_normal(g.proj_shape), prec)
+    G = tv.Geometry(g, prec)
+    xb = tv.backproject(G, to_dev(r, prec))
+    torch.cuda.synchronize()
+    ref = oracle.backproject(g, r)
+    got = xb.detach().cpu().double().numpy()
+    scale = np.max(np.abs(ref))
+    if prec == tv.F64:
+        assert np.max(np.abs(got - ref)) <= 1e-12 * scale
+    else:
+        # signed sums: FP32 rounding of the output plus FP64 summation order
+        assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) + 1e-9 * scale)
+
+
+@pytest.mark.parametrize("name", ["cone_ragged", "cone64", "small_parallel"])
+def test_gpu_adjoint_identity_fp64(name):
+    g = GEOMS[name]
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(g.vol_shape)
+    r = rng.standard_normal(g.proj_shape)
+    G = tv.Geometry(g, tv.F64)
+    ax = tv.project(G, to_dev(x, tv.F64)).cpu().numpy()
+    atr = tv.backproject(G, to_dev(r, tv.F64)).cpu().numpy()
+    lhs, rhs = float(np.sum(ax * r)), float(np.sum(x * atr))
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(r)
+
+
+@pytest.mark.parametrize("prec", [tv.F64, tv.F32])
+def test_backprojection_bitwise_reproducible(prec):
+    g = GEOMS["cone64"]
+    G = tv.Geometry(g, prec)
+    r = to_dev(np.random.default_rng(2).standard_normal(g.proj_shape), prec)
+    a = tv.backproject(G, r).clone()
+    b = tv.backproject(G, r).clone()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [tv.F64, tv.F32])
+@pytest.mark.parametrize("shape,tau,kind", [((5, 6, 7), 1e-4, "rand"), ((23, 29, 37), 1e-4, "rand"),
+                                            ((9, 8, 10), 1e-4, "box"), ((16, 16, 16), 0.5, "quad"),
+                                            ((1, 1, 1), 1e-4, "rand"), ((1, 7, 300), 1e-3, "rand")])
+def test_tv_matches_oracle(shape, tau, kind, prec):
+    if kind == "box":
+        x = np.zeros(shape)
+        x[2:6, 1:3, 3:6] = 0.7
+    elif kind == "quad":
+        x = 0.01 * synth.random_volume(shape, 4)
+    else:
+        x = synth.random_volume(shape, 5)
+    x = rounded(x, prec)
+    T_ref, g_ref = oracle.tv(x, tau)
+    g, T = tv.tv_grad(to_dev(x, prec), tau)
+    torch.cuda.synchronize()
+    T = float(T.item())
+    assert abs(T - T_ref) <= 1e-12 * max(T_ref, 1e-300) + 1e-300
+    got = g.cpu().double().numpy()
+    scale = max(np.max(np.abs(g_ref)), 1e-300)
+    tol = 1e-12 if prec == tv.F64 else 2e-6
+    assert np.max(np.abs(got - g_ref)) <= tol * scale
+
+
+@pytest.mark.parametrize("prec", [tv.F64, tv.F32])
+@pytest.mark.parametrize("name", ["small_parallel", "cone64", "cone_ragged"])
+def test_objective_grad_matches_oracle(name, prec):
+    g = GEOMS[name]
+    rng = np.random.default_rng(6)
+    x = rounded(synth.random_volume(g.vol_shape, 7), prec)
+    b = rounded(oracle.project(g, synth.random_volume(g.vol_shape, 8)) +
+                0.1 * rng.standard_normal(g.proj_shape), prec)
+    alpha, tau = 1e-2, 1e-4
+    f_ref, g_ref = oracle.phi_grad(g, b, alpha, tau, x)
+    G = tv.Geometry(g, prec)
+    phi, grad = tv.objective_grad(G, to_dev(b, prec), alpha, tau, to_dev(x, prec))
+    torch.cuda.synchronize()
+    f = float(phi.item())
+    got = grad.cpu().double().numpy()
+    scale = np.max(np.abs(g_ref))
+    if prec == tv.F64:
+        assert abs(f - f_ref) <= 1e-12 * f_ref
+        assert np.max(np.abs(got - g_ref)) <= 1e-11 * scale
+    else:
+        # the residual is stored in FP32 before the backprojection
+        assert abs(f - f_ref) <= 1e-9 * f_ref
+        assert np.max(np.abs(got - g_ref)) <= 1e-6 * scale
+
+
+# ---- full-size workload (256^3, 60 cone views of 384 x 256) ---------------
+
+@pytest.fixture(scope="module")
+def big():
+    w = synth.cfg_cone256()
+    return w
+
+
+def test_cone256_project_full(big):
+    g = big.geom
+    print("cone256 project", flush=True)
+    x = rounded(big.phantom(), tv.F32)
+    G = tv.Geometry(g, tv.F32)
+    y = tv.project(G, to_dev(x, tv.F32))
+    torch.cuda.synchronize()
+    check_close(y, oracle.project(g, x), tv.F32, "A x [cone256]")
+
+
+def test_cone256_backproject_full(big):
+    g = big.geom
+    print("cone256 backproject", flush=True)
+    r = rounded(np.random.default_rng(3).standard_normal(g.proj_shape), tv.F32)
+    G = tv.Geometry(g, tv.F32)
+    xb = tv.backproject(G, to_dev(r, tv.F32))
+    torch.cuda.synchronize()
+    ref = oracle.backproject(g, r)
+    got = xb.cpu().double().numpy()
+    scale = np.max(np.abs(ref))
+    assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) + 1e-9 * scale)
+
+
+def test_cone256_tv_full(big):
+    x = rounded(big.phantom(), tv.F32)
+    T_ref, g_ref = oracle.tv(x, big.tau)
+    g, T = tv.tv_grad(to_dev(x, tv.F32), big.tau)
+    torch.cuda.synchronize()
+    assert abs(float(T.item()) - T_ref) <= 1e-12 * T_ref
+    assert np.max(np.abs(g.cpu().double().numpy() - g_ref)) <= 2e-6 * np.max(np.abs(g_ref))
