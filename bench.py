@@ -55,6 +55,8 @@ def kernel_model(name: str, N: int, m: int, nnz: int, es: int):
         return "hbm", es * 3.0 * N, "GB/s", HBM_PEAK       # z, g in, xbar out
     if name == "extrapolate":
         return "hbm", es * 3.0 * (N + m) / 2.0, "GB/s", HBM_PEAK  # mean of the N and m launches
+    if name == "transpose":
+        return "hbm", es * 2.0 * N, "GB/s", HBM_PEAK       # volume in, y-fastest copy out
     raise KeyError(name)
 
 

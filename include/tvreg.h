@@ -185,7 +185,8 @@ typedef enum {
     TVREG_KERNEL_TV = 2,           /* TV gradient / value / Bregman stencil */
     TVREG_KERNEL_TRIAL = 3,        /* projected trial step with TV value */
     TVREG_KERNEL_EXTRAPOLATE = 4,  /* UPN extrapolation of x and of the residual */
-    TVREG_KERNEL_COUNT = 5
+    TVREG_KERNEL_TRANSPOSE = 5,    /* y-fastest copy of the volume read by the projector */
+    TVREG_KERNEL_COUNT = 6
 } tvreg_kernel_id;
 void tvreg_profile_enable(int32_t on);
 void tvreg_profile_reset(void);

@@ -62,7 +62,8 @@ EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
            "tvreg_solve_workspace_bytes", "tvreg_solve", "tvreg_profile_enable",
            "tvreg_profile_reset", "tvreg_profile_get", "tvreg_last_error", "tvreg_version")
 
-KERNELS = {"project": 0, "backproject": 1, "tv": 2, "trial": 3, "extrapolate": 4}
+KERNELS = {"project": 0, "backproject": 1, "tv": 2, "trial": 3, "extrapolate": 4,
+           "transpose": 5}
 
 
 def _load():

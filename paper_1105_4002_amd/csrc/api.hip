@@ -157,6 +157,8 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
             }
             e.invDx = e.Dx != 0.0 ? 1.0 / e.Dx : 0.0;
             e.invDy = e.Dy != 0.0 ? 1.0 / e.Dy : 0.0;
+            e.ox = -e.Sx * e.invDx;
+            e.oy = -e.Sy * e.invDy;
         }
         if (!cone)
             dn[v] = sqrt(c * c + s * s);
@@ -167,7 +169,7 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
         e.Sz = cone ? 0.0 : w;
         e.Dz = cone ? w : 0.0;
         e.invDz = e.Dz != 0.0 ? 1.0 / e.Dz : 0.0;
-        e.pad = 0.0;
+        e.oz = -e.Sz * e.invDz;
         if (cone)
             for (int col = 0; col < C; ++col) {
                 const double u = ((double)col - cu0) * d->pitch_u;
@@ -262,11 +264,11 @@ extern "C" tvreg_status tvreg_project(const tvreg_geometry *G, const void *x, vo
         return fail(TVREG_EDEVICE, "cannot select device %d", G->device);
     hipStream_t st = (hipStream_t)stream;
     if (G->prec == TVREG_F64)
-        TVR_HIP((launch_project<double>(G->g, (const double *)x, nullptr, (double *)y, nullptr,
-                                        nullptr, 0, st, nullptr)));
+        TVR_HIP((launch_project<double>(G->g, (const double *)x, nullptr, nullptr, (double *)y,
+                                        nullptr, nullptr, 0, st, nullptr)));
     else
-        TVR_HIP((launch_project<float>(G->g, (const float *)x, nullptr, (float *)y, nullptr,
-                                       nullptr, 0, st, nullptr)));
+        TVR_HIP((launch_project<float>(G->g, (const float *)x, nullptr, nullptr, (float *)y,
+                                       nullptr, nullptr, 0, st, nullptr)));
     return TVREG_OK;
 }
 
@@ -340,7 +342,7 @@ extern "C" tvreg_status tvreg_tv_grad(int32_t nx, int32_t ny, int32_t nz,
 namespace {
 
 struct Layout {
-    size_t vecN[5], vecM[3], partials, scalars, total;
+    size_t vecN[6], vecM[3], partials, scalars, total;  // vecN[5]: transposed copy
 };
 
 Layout solve_layout(const tvreg_geometry *G)
@@ -348,7 +350,7 @@ Layout solve_layout(const tvreg_geometry *G)
     Layout L{};
     const size_t es = elem_size(G->prec);
     size_t off = 0;
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < 6; ++i) {
         L.vecN[i] = off;
         off = align_up(off + es * (size_t)G->N, 256);
     }
@@ -486,12 +488,16 @@ struct Solver {
     int64_t N, m;
     T *vN[5];
     T *vM[3];
+    T *xt;  // y-fastest copy of the volume being projected
 
     tvreg_status project(const T *x, T *out, const T *rref)
     {
         int nb = 0;
+        TVR_HIP(run.timed(TVREG_KERNEL_TRANSPOSE,
+                          [&] { return launch_transpose_xy<T>(nx, ny, nz, x, xt, run.st); }));
         TVR_HIP(run.timed(TVREG_KERNEL_PROJECT, [&] {
-            return launch_project<T>(G->g, x, b, out, rref, run.part, run.pstride, run.st, &nb);
+            return launch_project<T>(G->g, x, xt, b, out, rref, run.part, run.pstride, run.st,
+                                     &nb);
         }));
         run.add(S_R2, nb);
         if (rref)
@@ -776,8 +782,8 @@ extern "C" size_t tvreg_objective_workspace_bytes(const tvreg_geometry *G)
 {
     if (!G)
         return 0;
-    return align_up(elem_size(G->prec) * (size_t)G->m, 256) + partial_bytes(G->pstride) +
-           256;
+    return align_up(elem_size(G->prec) * (size_t)G->m, 256) +
+           align_up(elem_size(G->prec) * (size_t)G->N, 256) + partial_bytes(G->pstride) + 256;
 }
 
 template <typename T>
@@ -785,10 +791,12 @@ static tvreg_status objective_impl(const tvreg_geometry *G, const T *b, double a
                                    const T *x, T *grad, double *phi, char *ws, hipStream_t st)
 {
     T *r = (T *)ws;
-    double *part = (double *)(ws + align_up(sizeof(T) * (size_t)G->m, 256));
+    T *xt = (T *)(ws + align_up(sizeof(T) * (size_t)G->m, 256));
+    double *part = (double *)((char *)xt + align_up(sizeof(T) * (size_t)G->N, 256));
     double *sc = (double *)((char *)part + partial_bytes(G->pstride));
     int nb1 = 0, nb2 = 0;
-    TVR_HIP(launch_project<T>(G->g, x, b, r, nullptr, part, G->pstride, st, &nb1));
+    TVR_HIP(launch_transpose_xy<T>(G->g.nx, G->g.ny, G->g.nz, x, xt, st));
+    TVR_HIP(launch_project<T>(G->g, x, xt, b, r, nullptr, part, G->pstride, st, &nb1));
     TVR_HIP(launch_backproject<T>(G->g, r, grad, st));
     TVR_HIP(launch_tv<T>(G->g.nx, G->g.ny, G->g.nz, tau, alpha, x, nullptr, grad, grad, part,
                          G->pstride, st, &nb2));
@@ -845,6 +853,7 @@ static tvreg_status solve_impl(const tvreg_geometry *G, const T *b, const tvreg_
     s.m = G->m;
     for (int i = 0; i < 5; ++i)
         s.vN[i] = (T *)(ws + L.vecN[i]);
+    s.xt = (T *)(ws + L.vecN[5]);
     for (int i = 0; i < 3; ++i)
         s.vM[i] = (T *)(ws + L.vecM[i]);
     s.run.G = G;

@@ -21,94 +21,96 @@ namespace {
 constexpr int PJ_TX = 64;  // detector columns per block (one wavefront)
 constexpr int PJ_TY = 4;   // detector rows per block
 
+// Slab entry/exit of the ray with the volume along one axis; a ray parallel
+// to the axis (invD = 0) is inside iff S lies in the half-open range.
+__device__ __forceinline__ void slab(double lo, double hi, double S, double invD, double o,
+                                     double &tmin, double &tmax, bool &hit)
+{
+    if (invD != 0.0) {
+        const double t0 = plane_t(lo, invD, o), t1 = plane_t(hi, invD, o);
+        tmin = fmax(tmin, fmin(t0, t1));
+        tmax = fmin(tmax, fmax(t0, t1));
+    } else {
+        hit = hit && (S >= lo) && (S < hi);
+    }
+}
+
 // Sum of dt * x along the ray inside the volume, dt in units of the ray
-// parameter (multiply by |D| for lengths).  t(X) = (X - S) * invD is the
-// plane-crossing formula shared with the backprojector.
+// parameter (multiply by |D| for lengths).  Walks voxel to voxel: the next
+// crossing of each axis is plane_t(X) of the next plane X, the segment ends
+// at the nearest one, and every axis whose crossing is reached advances (a
+// tie of two axes is one crossing, so no zero-length piece is visited).
+// The exit crossing of each axis is computed with the same formula as the
+// slab exit, so no index leaves the volume before t reaches tmax.
+// The volume is read through strides (sx, sy) so that a y-fastest copy can
+// serve views whose rays run mostly along x (adjacent detector columns then
+// touch adjacent addresses).
 template <typename T, bool CONE>
 __device__ __forceinline__ double ray_walk(const GeomDev &g, const T *__restrict__ x,
-                                           double Sx, double Sy, double Sz, double Dx,
-                                           double Dy, double Dz, double iDx, double iDy,
-                                           double iDz)
+                                           const ColEntry &ce, const RowEntry &re, int sx,
+                                           int sy)
 {
     const double lox = -g.hx, loy = -g.hy, loz = -g.hz;
     double tmin = CONE ? 0.0 : -INFINITY;
     double tmax = CONE ? 1.0 : INFINITY;
     bool hit = true;
-    if (Dx != 0.0) {
-        double t0 = (lox - Sx) * iDx, t1 = (lox + (double)g.nx - Sx) * iDx;
-        tmin = fmax(tmin, fmin(t0, t1));
-        tmax = fmin(tmax, fmax(t0, t1));
-    } else {
-        hit = hit && (Sx >= lox) && (Sx < lox + (double)g.nx);
-    }
-    if (Dy != 0.0) {
-        double t0 = (loy - Sy) * iDy, t1 = (loy + (double)g.ny - Sy) * iDy;
-        tmin = fmax(tmin, fmin(t0, t1));
-        tmax = fmin(tmax, fmax(t0, t1));
-    } else {
-        hit = hit && (Sy >= loy) && (Sy < loy + (double)g.ny);
-    }
-    if (Dz != 0.0) {
-        double t0 = (loz - Sz) * iDz, t1 = (loz + (double)g.nz - Sz) * iDz;
-        tmin = fmax(tmin, fmin(t0, t1));
-        tmax = fmin(tmax, fmax(t0, t1));
-    } else {
-        hit = hit && (Sz >= loz) && (Sz < loz + (double)g.nz);
-    }
+    slab(lox, g.hx, ce.Sx, ce.invDx, ce.ox, tmin, tmax, hit);
+    slab(loy, g.hy, ce.Sy, ce.invDy, ce.oy, tmin, tmax, hit);
+    slab(loz, g.hz, re.Sz, re.invDz, re.oz, tmin, tmax, hit);
     if (!hit || !(tmax > tmin))
         return 0.0;
 
-    // first voxel: the entry point, clamped into the grid
-    // (an axis the ray runs parallel to keeps its coordinate; the clamp also
-    // guards against S - lo rounding up to the upper face)
-    int ix = (int)floor((Dx != 0.0 ? Sx + tmin * Dx : Sx) - lox);
-    int iy = (int)floor((Dy != 0.0 ? Sy + tmin * Dy : Sy) - loy);
-    int iz = (int)floor((Dz != 0.0 ? Sz + tmin * Dz : Sz) - loz);
+    // entry voxel (an axis the ray runs parallel to keeps its coordinate;
+    // the clamp absorbs rounding at the entry face)
+    int ix = (int)floor((ce.invDx != 0.0 ? ce.Sx + tmin * ce.Dx : ce.Sx) - lox);
+    int iy = (int)floor((ce.invDy != 0.0 ? ce.Sy + tmin * ce.Dy : ce.Sy) - loy);
+    int iz = (int)floor((re.invDz != 0.0 ? re.Sz + tmin * re.Dz : re.Sz) - loz);
     ix = min(max(ix, 0), g.nx - 1);
     iy = min(max(iy, 0), g.ny - 1);
     iz = min(max(iz, 0), g.nz - 1);
 
-    const int sx = Dx > 0.0 ? 1 : -1, sy = Dy > 0.0 ? 1 : -1, sz = Dz > 0.0 ? 1 : -1;
-    const int ox = Dx > 0.0 ? 1 : 0, oy = Dy > 0.0 ? 1 : 0, oz = Dz > 0.0 ? 1 : 0;
-    double tnx = Dx != 0.0 ? (lox + (double)(ix + ox) - Sx) * iDx : INFINITY;
-    double tny = Dy != 0.0 ? (loy + (double)(iy + oy) - Sy) * iDy : INFINITY;
-    double tnz = Dz != 0.0 ? (loz + (double)(iz + oz) - Sz) * iDz : INFINITY;
-    const int stx = sx, sty = sy * g.nx, stz = sz * g.nx * g.ny;
-    int idx = ix + g.nx * (iy + g.ny * iz);
+    const bool px = ce.Dx > 0.0, py = ce.Dy > 0.0, pz = re.Dz > 0.0;
+    const double sxd = px ? 1.0 : -1.0, syd = py ? 1.0 : -1.0, szd = pz ? 1.0 : -1.0;
+    double Xn = lox + (double)(ix + (px ? 1 : 0));
+    double Yn = loy + (double)(iy + (py ? 1 : 0));
+    double Zn = loz + (double)(iz + (pz ? 1 : 0));
+    double tnx = ce.invDx != 0.0 ? plane_t(Xn, ce.invDx, ce.ox) : INFINITY;
+    double tny = ce.invDy != 0.0 ? plane_t(Yn, ce.invDy, ce.oy) : INFINITY;
+    double tnz = re.invDz != 0.0 ? plane_t(Zn, re.invDz, re.oz) : INFINITY;
+    const int sz = g.nx * g.ny;
+    const int stx = px ? sx : -sx;
+    const int sty = py ? sy : -sy;
+    const int stz = pz ? sz : -sz;
+    const unsigned last = (unsigned)(g.nx * g.ny * g.nz - 1);
+    int idx = ix * sx + iy * sy + iz * sz;
 
     double t = tmin, acc = 0.0;
-    // every pass advances at least one index monotonically, so the walk
-    // ends after at most nx + ny + nz passes
-    const int cap = g.nx + g.ny + g.nz + 2;
-    for (int it = 0; it < cap && t < tmax; ++it) {
+    const int cap = g.nx + g.ny + g.nz + 2;  // hard bound on the number of voxels
+    for (int it = 0; it < cap; ++it) {
         const double tn = fmin(fmin(tnx, tny), fmin(tnz, tmax));
-        acc += fmax(tn - t, 0.0) * (double)x[idx];
-        t = fmax(t, tn);
-        const bool ax = tnx <= tn, ay = tny <= tn, az = tnz <= tn;
-        if (ax) {
-            ix += sx;
-            idx += stx;
-            tnx = (lox + (double)(ix + ox) - Sx) * iDx;
-        }
-        if (ay) {
-            iy += sy;
-            idx += sty;
-            tny = (loy + (double)(iy + oy) - Sy) * iDy;
-        }
-        if (az) {
-            iz += sz;
-            idx += stz;
-            tnz = (loz + (double)(iz + oz) - Sz) * iDz;
-        }
-        if ((unsigned)ix >= (unsigned)g.nx || (unsigned)iy >= (unsigned)g.ny ||
-            (unsigned)iz >= (unsigned)g.nz)
+        acc = fma(fmax(tn - t, 0.0), (double)x[min((unsigned)idx, last)], acc);
+        t = tn;
+        if (!(t < tmax))
             break;
+        const bool ax = tnx <= tn, ay = tny <= tn, az = tnz <= tn;
+        idx += (ax ? stx : 0) + (ay ? sty : 0) + (az ? stz : 0);
+        const double Xa = Xn + sxd, Ya = Yn + syd, Za = Zn + szd;
+        const double ta = plane_t(Xa, ce.invDx, ce.ox);
+        const double tb = plane_t(Ya, ce.invDy, ce.oy);
+        const double tc = plane_t(Za, re.invDz, re.oz);
+        Xn = ax ? Xa : Xn;
+        Yn = ay ? Ya : Yn;
+        Zn = az ? Za : Zn;
+        tnx = ax ? ta : tnx;
+        tny = ay ? tb : tny;
+        tnz = az ? tc : tnz;
     }
     return acc;
 }
 
 template <typename T, bool CONE>
 __global__ __launch_bounds__(PJ_TX *PJ_TY) void project_kernel(GeomDev g, const T *__restrict__ x,
+                                                              const T *__restrict__ xt,
                                                               const T *__restrict__ b,
                                                               T *__restrict__ out,
                                                               const T *__restrict__ rref,
@@ -122,8 +124,11 @@ __global__ __launch_bounds__(PJ_TX *PJ_TY) void project_kernel(GeomDev g, const 
     if (col < g.cols && row < g.rows) {
         const ColEntry ce = g.col[(size_t)v * g.cols + col];
         const RowEntry re = g.row[row];
-        double s = ray_walk<T, CONE>(g, x, ce.Sx, ce.Sy, re.Sz, ce.Dx, ce.Dy, re.Dz, ce.invDx,
-                                     ce.invDy, re.invDz);
+        // rays mostly along x read the y-fastest copy when one is given
+        const double cv = g.cs[v].x, sv = g.cs[v].y;
+        const bool use_t = xt != nullptr && fabs(cv) > fabs(sv);
+        const double s = ray_walk<T, CONE>(g, use_t ? xt : x, ce, re, use_t ? g.ny : 1,
+                                           use_t ? 1 : g.nx);
         const double dn = CONE ? g.dnorm[(size_t)row * g.cols + col] : g.dnorm[v];
         const size_t i = ((size_t)v * g.rows + row) * g.cols + col;
         double ri = s * dn;
@@ -145,19 +150,20 @@ __global__ __launch_bounds__(PJ_TX *PJ_TY) void project_kernel(GeomDev g, const 
 }  // namespace
 
 template <typename T>
-hipError_t launch_project(const GeomDev &g, const T *x, const T *b, T *out, const T *rref,
-                          double *partials, int pstride, hipStream_t st, int *nblocks)
+hipError_t launch_project(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,
+                          const T *rref, double *partials, int pstride, hipStream_t st,
+                          int *nblocks)
 {
     dim3 block(PJ_TX, PJ_TY, 1);
     dim3 grid((g.cols + PJ_TX - 1) / PJ_TX, (g.rows + PJ_TY - 1) / PJ_TY, g.nviews);
     if (nblocks)
         *nblocks = (int)(grid.x * grid.y * grid.z);
     if (g.cone)
-        hipLaunchKernelGGL((project_kernel<T, true>), grid, block, 0, st, g, x, b, out, rref,
-                           partials, pstride);
+        hipLaunchKernelGGL((project_kernel<T, true>), grid, block, 0, st, g, x, xt, b, out,
+                           rref, partials, pstride);
     else
-        hipLaunchKernelGGL((project_kernel<T, false>), grid, block, 0, st, g, x, b, out, rref,
-                           partials, pstride);
+        hipLaunchKernelGGL((project_kernel<T, false>), grid, block, 0, st, g, x, xt, b, out,
+                           rref, partials, pstride);
     return hipGetLastError();
 }
 
@@ -166,10 +172,11 @@ int project_blocks(const GeomDev &g)
     return ((g.cols + PJ_TX - 1) / PJ_TX) * ((g.rows + PJ_TY - 1) / PJ_TY) * g.nviews;
 }
 
-template hipError_t launch_project<float>(const GeomDev &, const float *, const float *, float *,
-                                          const float *, double *, int, hipStream_t, int *);
+template hipError_t launch_project<float>(const GeomDev &, const float *, const float *,
+                                          const float *, float *, const float *, double *, int,
+                                          hipStream_t, int *);
 template hipError_t launch_project<double>(const GeomDev &, const double *, const double *,
-                                           double *, const double *, double *, int, hipStream_t,
-                                           int *);
+                                           const double *, double *, const double *, double *,
+                                           int, hipStream_t, int *);
 
 }  // namespace tvr

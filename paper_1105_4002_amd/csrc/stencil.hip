@@ -205,6 +205,33 @@ __global__ __launch_bounds__(VB) void trial_kernel(int nx, int ny, int nz, doubl
 
 constexpr int EW_MAX_BLOCKS = 4096;
 
+// xt[z][x][y] = x[z][y][x] through a 32 x 32 LDS tile per block (both the
+// read and the write are coalesced); the padding column avoids bank conflicts.
+constexpr int TR = 32;
+
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_xy_kernel(int nx, int ny, const T *__restrict__ x,
+                                                           T *__restrict__ xt)
+{
+    __shared__ T tile[TR][TR + 1];
+    const size_t plane = (size_t)nx * ny;
+    const T *xs = x + (size_t)blockIdx.z * plane;
+    T *xd = xt + (size_t)blockIdx.z * plane;
+    const int bx = blockIdx.x * TR, by = blockIdx.y * TR;
+    const int tx = threadIdx.x % TR, ty = threadIdx.x / TR;  // 32 x 8 threads
+    for (int j = ty; j < TR; j += 8) {
+        const int ix = bx + tx, iy = by + j;
+        if (ix < nx && iy < ny)
+            tile[j][tx] = xs[(size_t)iy * nx + ix];
+    }
+    __syncthreads();
+    for (int j = ty; j < TR; j += 8) {
+        const int iy = by + tx, ix = bx + j;
+        if (ix < nx && iy < ny)
+            xd[(size_t)ix * ny + iy] = tile[tx][j];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(VB) void extrapolate_kernel(int64_t n, double beta,
                                                          const T *__restrict__ xn,
@@ -353,6 +380,14 @@ hipError_t launch_bb_dots(int64_t n, const T *x, const T *xp, const T *g, const 
 }
 
 template <typename T>
+hipError_t launch_transpose_xy(int nx, int ny, int nz, const T *x, T *xt, hipStream_t st)
+{
+    dim3 grid((nx + TR - 1) / TR, (ny + TR - 1) / TR, nz);
+    hipLaunchKernelGGL((transpose_xy_kernel<T>), grid, dim3(256), 0, st, nx, ny, x, xt);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_clip(int64_t n, const T *in, T *out, hipStream_t st)
 {
     hipLaunchKernelGGL((clip_kernel<T>), dim3(elementwise_blocks(n)), dim3(VB), 0, st, n, in, out);
@@ -384,7 +419,8 @@ hipError_t launch_combine_phi(const double *r2, const double *tv, double alpha, 
                                               double *, int, hipStream_t, int *);               \
     template hipError_t launch_bb_dots<T>(int64_t, const T *, const T *, const T *, const T *,  \
                                           double *, int, hipStream_t, int *);                   \
-    template hipError_t launch_clip<T>(int64_t, const T *, T *, hipStream_t);
+    template hipError_t launch_clip<T>(int64_t, const T *, T *, hipStream_t);                   \
+    template hipError_t launch_transpose_xy<T>(int, int, int, const T *, T *, hipStream_t);
 
 TVR_INST(float)
 TVR_INST(double)

@@ -12,14 +12,21 @@ namespace tvr {
 // the source to the pixel, for a parallel beam t is unbounded and D is the
 // unit view direction.  The in-plane part (x, y) depends on (view, column),
 // the axial part (z) on the detector row only.  Both the projector and the
-// gather backprojector evaluate plane crossings as t(X) = (X - S) * invD
-// from these same tables, so A and A^T use identical FP64 lengths.
+// gather backprojector evaluate the crossing of the plane at coordinate X as
+// t(X) = fma(X, invD, o) with o = -S * invD from these same tables, so A and
+// A^T use bitwise identical FP64 crossing parameters.  invD = 0 marks a ray
+// parallel to that axis (membership of S in the half-open cell decides).
 struct ColEntry {
-    double Sx, Sy, Dx, Dy, invDx, invDy;
+    double Sx, Sy, Dx, Dy, invDx, invDy, ox, oy;
 };
 struct RowEntry {
-    double Sz, Dz, invDz, pad;
+    double Sz, Dz, invDz, oz;
 };
+
+__host__ __device__ __forceinline__ double plane_t(double X, double invD, double o)
+{
+    return fma(X, invD, o);
+}
 
 struct GeomDev {
     int nx, ny, nz;
@@ -66,9 +73,16 @@ struct SlotList {
 // All return hipSuccess or the launch error.  `T` is float (FP32 storage with
 // FP64 reductions) or double.
 
+// out = A x (- b); xt, when not NULL, is the same volume stored y fastest
+// ([z][x][y]) and serves the views whose rays run mostly along x.
 template <typename T>
-hipError_t launch_project(const GeomDev &g, const T *x, const T *b, T *out, const T *rref,
-                          double *partials, int pstride, hipStream_t st, int *nblocks);
+hipError_t launch_project(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,
+                          const T *rref, double *partials, int pstride, hipStream_t st,
+                          int *nblocks);
+
+// xt[z][x][y] = x[z][y][x]
+template <typename T>
+hipError_t launch_transpose_xy(int nx, int ny, int nz, const T *x, T *xt, hipStream_t st);
 
 template <typename T>
 hipError_t launch_backproject(const GeomDev &g, const T *r, T *out, hipStream_t st);
