@@ -1,14 +1,19 @@
 // Voxel-space kernels: the smoothed-TV stencil (value, gradient, Bregman
 // distance), the projected trial step, UPN's extrapolation, the
-// Barzilai-Borwein inner products and the slot finaliser.
+// Barzilai-Borwein inner products, the y-fastest transpose and the slot
+// finaliser.
 //
 // TV (eq. 2, Huber-smoothed with parameter tau):
 //   T_tau(x) = sum_j Phi(D_j x),  Phi(z) = |z| - tau/2 (|z| >= tau),
 //   |z|^2 / (2 tau) otherwise, D_j x = forward differences along x, y, z,
 //   a component being 0 where the neighbour is outside the volume;
 //   grad T_tau(x) = sum_j D_j^T q_j,  q_j = D_j x / max(tau, |D_j x|).
-// The gradient stencil runs in the storage type T; Phi values, Bregman
-// distances and every sum run in double.
+// The stencil arithmetic (differences, q, per-voxel Phi and Bregman terms)
+// runs in the storage type T -- with one hardware reciprocal square root per
+// normalisation for float -- and every sum over voxels runs in double.
+//
+// The TV and trial kernels give each thread one (x, y) column and march up
+// a chunk of z, carrying the values the next plane reuses.
 #include "reduce.hpp"
 #include "tvreg_internal.hpp"
 
@@ -16,121 +21,165 @@ namespace tvr {
 
 namespace {
 
-constexpr int VB = 256;  // threads per block for voxel kernels
+constexpr int VB = 256;    // threads per block for 1-D kernels
+constexpr int VX = 64;     // voxel kernels: block of 64 x 4 columns ...
+constexpr int VY = 4;
+constexpr int VZ = 16;     // ... each marching up 16 voxels
 
-__device__ __forceinline__ double huber(double n, double tau)
+// Math in the stencil's precision.
+template <typename C>
+struct SM;
+
+template <>
+struct SM<float> {
+    // 1 / max(tau, |v|) from |v|^2 (rsq(0) = +inf selects 1/tau)
+    static __device__ __forceinline__ float inv_clamped(float d2, float tau, float itau)
+    {
+        return fminf(__builtin_amdgcn_rsqf(d2), itau);
+    }
+    static __device__ __forceinline__ float norm(float d2)
+    {
+        return d2 > 0.f ? d2 * __builtin_amdgcn_rsqf(d2) : 0.f;
+    }
+    static __device__ __forceinline__ float inv(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+
+template <>
+struct SM<double> {
+    static __device__ __forceinline__ double inv_clamped(double d2, double tau, double)
+    {
+        return 1.0 / fmax(sqrt(d2), tau);
+    }
+    static __device__ __forceinline__ double norm(double d2) { return sqrt(d2); }
+    static __device__ __forceinline__ double inv(double x) { return 1.0 / x; }
+};
+
+template <typename C>
+__device__ __forceinline__ C huber_c(C d2, C tau, C itau)
 {
-    return n >= tau ? n - 0.5 * tau : n * n / (2.0 * tau);
+    const C n = SM<C>::norm(d2);
+    return n >= tau ? n - C(0.5) * tau : C(0.5) * d2 * itau;
 }
 
 // Bregman distance Phi(a) - Phi(b) - grad Phi(b)^T (a - b) with d = a - b,
 // written per smoothing regime so that it is formed from d without
-// cancellation (each case follows from |a|^2 = |b|^2 + 2 b.d + |d|^2).
-__device__ __forceinline__ double huber_bregman(double a0, double a1, double a2, double b0,
-                                                double b1, double b2, double d0, double d1,
-                                                double d2, double tau)
+// cancellation (each case follows from |a|^2 = |b|^2 + 2 b.d + |d|^2):
+//   both quadratic: |d|^2 / (2 tau);  both linear: |a|/2 |a/|a| - b/|b||^2;
+//   a linear, b quadratic: (|d|^2 - (|a| - tau)^2) / (2 tau);
+//   a quadratic, b linear: |a - tau b/|b||^2 / (2 tau).
+template <typename C>
+__device__ __forceinline__ C huber_bregman(C a0, C a1, C a2, C b0, C b1, C b2, C d0, C d1, C d2,
+                                           C tau, C itau)
 {
-    const double na = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
-    const double nb = sqrt(b0 * b0 + b1 * b1 + b2 * b2);
-    const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+    const C na = SM<C>::norm(a0 * a0 + a1 * a1 + a2 * a2);
+    const C nb = SM<C>::norm(b0 * b0 + b1 * b1 + b2 * b2);
+    const C dd = d0 * d0 + d1 * d1 + d2 * d2;
     if (na < tau && nb < tau)
-        return dd / (2.0 * tau);
+        return C(0.5) * dd * itau;
     if (na >= tau && nb >= tau) {
-        // |a| (1 - cos) = |a|/2 |a/|a| - b/|b||^2, the unit-vector difference
-        // expanded as d/|a| - (b/|b|) ((a + b).d) / (|a| (|a| + |b|))
-        const double sc = ((a0 + b0) * d0 + (a1 + b1) * d1 + (a2 + b2) * d2) / (na * (na + nb));
-        const double ib = 1.0 / nb, ia = 1.0 / na;
-        const double e0 = d0 * ia - b0 * ib * sc;
-        const double e1 = d1 * ia - b1 * ib * sc;
-        const double e2 = d2 * ia - b2 * ib * sc;
-        return 0.5 * na * (e0 * e0 + e1 * e1 + e2 * e2);
+        // unit-vector difference d/|a| - (b/|b|) ((a + b).d) / (|a| (|a| + |b|))
+        const C ia = SM<C>::inv(na), ib = SM<C>::inv(nb);
+        const C sc = ((a0 + b0) * d0 + (a1 + b1) * d1 + (a2 + b2) * d2) * ia * SM<C>::inv(na + nb);
+        const C e0 = d0 * ia - b0 * ib * sc;
+        const C e1 = d1 * ia - b1 * ib * sc;
+        const C e2 = d2 * ia - b2 * ib * sc;
+        return C(0.5) * na * (e0 * e0 + e1 * e1 + e2 * e2);
     }
     if (na >= tau) {
-        const double t = na - tau;
-        return fmax((dd - t * t) / (2.0 * tau), 0.0);
+        const C t = na - tau;
+        const C v = C(0.5) * (dd - t * t) * itau;
+        return v > C(0) ? v : C(0);
     }
-    const double ib = tau / nb;
-    const double e0 = a0 - b0 * ib, e1 = a1 - b1 * ib, e2 = a2 - b2 * ib;
-    return (e0 * e0 + e1 * e1 + e2 * e2) / (2.0 * tau);
+    const C s = tau * SM<C>::inv(nb);
+    const C e0 = a0 - b0 * s, e1 = a1 - b1 * s, e2 = a2 - b2 * s;
+    return C(0.5) * (e0 * e0 + e1 * e1 + e2 * e2) * itau;
 }
 
-// q = D / max(tau, |D|) at voxel j in storage precision
+// gout = (gin ? gin : 0) + alpha grad T(y); with partials also the sums
+// T(y) and, with xref, Bregman_T(xref, y) and |xref - y|^2.
 template <typename T>
-__device__ __forceinline__ void qvec(const T *__restrict__ y, size_t j, bool hx, bool hy, bool hz,
-                                     size_t sy, size_t sz, T tau, T &qx, T &qy, T &qz)
+__global__ __launch_bounds__(VX *VY) void tv_kernel(int nx, int ny, int nz, double tau,
+                                                    double alpha, const T *__restrict__ y,
+                                                    const T *__restrict__ xref,
+                                                    const T *__restrict__ gin,
+                                                    T *__restrict__ gout,
+                                                    double *__restrict__ partials, int pstride)
 {
-    const T yj = y[j];
-    const T dx = hx ? y[j + 1] - yj : T(0);
-    const T dy = hy ? y[j + sy] - yj : T(0);
-    const T dz = hz ? y[j + sz] - yj : T(0);
-    const T n = sqrt(dx * dx + dy * dy + dz * dz);
-    const T den = n > tau ? n : tau;
-    qx = dx / den;
-    qy = dy / den;
-    qz = dz / den;
-}
-
-template <typename T>
-__global__ __launch_bounds__(VB) void tv_kernel(int nx, int ny, int nz, double tau, double alpha,
-                                                const T *__restrict__ y,
-                                                const T *__restrict__ xref,
-                                                const T *__restrict__ gin, T *__restrict__ gout,
-                                                double *__restrict__ partials, int pstride)
-{
-    const size_t N = (size_t)nx * ny * nz;
-    const size_t j = (size_t)blockIdx.x * VB + threadIdx.x;
+    const int ix = blockIdx.x * VX + threadIdx.x;
+    const int iy = blockIdx.y * VY + threadIdx.y;
+    const int z0 = blockIdx.z * VZ;
+    const int z1 = min(z0 + VZ, nz);
     double red[3] = {0.0, 0.0, 0.0};
-    if (j < N) {
+    if (ix < nx && iy < ny) {
+        const T ct = (T)tau, itau = T(1) / ct;
         const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-        const int ix = (int)(j % nx);
-        const int iy = (int)((j / nx) % ny);
-        const int iz = (int)(j / sz);
-        const bool hx = ix + 1 < nx, hy = iy + 1 < ny, hz = iz + 1 < nz;
-        const T tt = (T)tau;
-        // own differences (value, Bregman, own q)
-        const T yj = y[j];
-        const T dx = hx ? y[j + 1] - yj : T(0);
-        const T dy = hy ? y[j + sy] - yj : T(0);
-        const T dz = hz ? y[j + sz] - yj : T(0);
-        // the value's differences are formed in double (exact for FP32 data)
-        const double yd = (double)yj;
-        const double b0 = hx ? (double)y[j + 1] - yd : 0.0;
-        const double b1 = hy ? (double)y[j + sy] - yd : 0.0;
-        const double b2 = hz ? (double)y[j + sz] - yd : 0.0;
-        red[0] = huber(sqrt(b0 * b0 + b1 * b1 + b2 * b2), tau);
-        if (gout) {
-            const T n = sqrt(dx * dx + dy * dy + dz * dz);
-            const T den = n > tt ? n : tt;
-            T gj = -(dx + dy + dz) / den;
-            T qx, qy, qz;
-            if (ix > 0) {
-                qvec(y, j - 1, true, hy, hz, sy, sz, tt, qx, qy, qz);
-                gj += qx;
-            }
-            if (iy > 0) {
-                qvec(y, j - sy, hx, true, hz, sy, sz, tt, qx, qy, qz);
-                gj += qy;
-            }
-            if (iz > 0) {
-                qvec(y, j - sz, hx, hy, true, sy, sz, tt, qx, qy, qz);
-                gj += qz;
-            }
-            if (gin)
-                gout[j] = (T)((double)gin[j] + alpha * (double)gj);
-            else
-                gout[j] = (T)(alpha * (double)gj);
+        const bool hx = ix + 1 < nx, hy = iy + 1 < ny, lx = ix > 0, ly = iy > 0;
+        // z component of q at the voxel below the chunk
+        T qz_prev = T(0);
+        if (z0 > 0) {
+            const size_t jb = (size_t)ix + sy * iy + sz * (z0 - 1);
+            const T yb = y[jb];
+            const T dx = hx ? y[jb + 1] - yb : T(0);
+            const T dy = hy ? y[jb + sy] - yb : T(0);
+            const T dz = y[jb + sz] - yb;
+            qz_prev = dz * SM<T>::inv_clamped(dx * dx + dy * dy + dz * dz, ct, itau);
         }
-        if (xref) {
-            const double ej = (double)xref[j] - (double)yj;
-            const double xj = (double)xref[j];
-            const double a0 = hx ? (double)xref[j + 1] - xj : 0.0;
-            const double a1 = hy ? (double)xref[j + sy] - xj : 0.0;
-            const double a2 = hz ? (double)xref[j + sz] - xj : 0.0;
-            const double d0 = hx ? ((double)xref[j + 1] - (double)y[j + 1]) - ej : 0.0;
-            const double d1 = hy ? ((double)xref[j + sy] - (double)y[j + sy]) - ej : 0.0;
-            const double d2 = hz ? ((double)xref[j + sz] - (double)y[j + sz]) - ej : 0.0;
-            red[1] = huber_bregman(a0, a1, a2, b0, b1, b2, d0, d1, d2, tau);
-            red[2] = ej * ej;
+        for (int z = z0; z < z1; ++z) {
+            const size_t j = (size_t)ix + sy * iy + sz * z;
+            const bool hz = z + 1 < nz;
+            const T yj = y[j];
+            const T dx = hx ? y[j + 1] - yj : T(0);
+            const T dy = hy ? y[j + sy] - yj : T(0);
+            const T dz = hz ? y[j + sz] - yj : T(0);
+            const T d2 = dx * dx + dy * dy + dz * dz;
+            const T inv = SM<T>::inv_clamped(d2, ct, itau);
+            T gsum = -(dx + dy + dz) * inv + qz_prev;
+            qz_prev = dz * inv;
+            if (lx) {  // x component of q at the voxel on the left
+                const size_t k = j - 1;
+                const T yk = y[k];
+                const T ex = yj - yk;
+                const T ey = hy ? y[k + sy] - yk : T(0);
+                const T ez = hz ? y[k + sz] - yk : T(0);
+                gsum += ex * SM<T>::inv_clamped(ex * ex + ey * ey + ez * ez, ct, itau);
+            }
+            if (ly) {  // y component of q at the voxel in front
+                const size_t k = j - sy;
+                const T yk = y[k];
+                const T ex = hx ? y[k + 1] - yk : T(0);
+                const T ey = yj - yk;
+                const T ez = hz ? y[k + sz] - yk : T(0);
+                gsum += ey * SM<T>::inv_clamped(ex * ex + ey * ey + ez * ez, ct, itau);
+            }
+            if (gout)
+                gout[j] = gin ? (T)((double)gin[j] + alpha * (double)gsum)
+                              : (T)(alpha * (double)gsum);
+            if (partials) {
+                red[0] += (double)huber_c<T>(d2, ct, itau);
+                if (xref) {
+                    const T xj = xref[j];
+                    const T ej = xj - yj;
+                    T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
+                    if (hx) {
+                        const T xn = xref[j + 1];
+                        a0 = xn - xj;
+                        e0 = (xn - y[j + 1]) - ej;
+                    }
+                    if (hy) {
+                        const T xn = xref[j + sy];
+                        a1 = xn - xj;
+                        e1 = (xn - y[j + sy]) - ej;
+                    }
+                    if (hz) {
+                        const T xn = xref[j + sz];
+                        a2 = xn - xj;
+                        e2 = (xn - y[j + sz]) - ej;
+                    }
+                    red[1] += (double)huber_bregman<T>(a0, a1, a2, dx, dy, dz, e0, e1, e2, ct, itau);
+                    const double ed = (double)xj - (double)yj;
+                    red[2] += ed * ed;
+                }
+            }
         }
     }
     if (partials) {
@@ -146,57 +195,54 @@ __device__ __forceinline__ T pstep(const T *__restrict__ z, const T *__restrict_
     return (T)fmax((double)z[k] - step * (double)g[k], 0.0);
 }
 
+// xbar = P_Q(z - step g) (Q = nonnegative orthant) with the sums |xbar - z|^2,
+// g^T (z - xbar), T(xbar), Bregman_T(xbar, z) and, for gm_step > 0,
+// |z - P_Q(z - gm_step g)|^2 (the GPBB gradient map).
 template <typename T>
-__global__ __launch_bounds__(VB) void trial_kernel(int nx, int ny, int nz, double tau,
-                                                   const T *__restrict__ z,
-                                                   const T *__restrict__ g, double step,
-                                                   double gm_step, T *__restrict__ xbar,
-                                                   double *__restrict__ partials, int pstride)
+__global__ __launch_bounds__(VX *VY) void trial_kernel(int nx, int ny, int nz, double tau,
+                                                       const T *__restrict__ zv,
+                                                       const T *__restrict__ g, double step,
+                                                       double gm_step, T *__restrict__ xbar,
+                                                       double *__restrict__ partials,
+                                                       int pstride)
 {
-    const size_t N = (size_t)nx * ny * nz;
-    const size_t j = (size_t)blockIdx.x * VB + threadIdx.x;
+    const int ix = blockIdx.x * VX + threadIdx.x;
+    const int iy = blockIdx.y * VY + threadIdx.y;
+    const int z0 = blockIdx.z * VZ;
+    const int z1 = min(z0 + VZ, nz);
     double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (j < N) {
+    if (ix < nx && iy < ny) {
+        const T ct = (T)tau, itau = T(1) / ct;
         const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-        const int ix = (int)(j % nx);
-        const int iy = (int)((j / nx) % ny);
-        const int iz = (int)(j / sz);
-        const bool hx = ix + 1 < nx, hy = iy + 1 < ny, hz = iz + 1 < nz;
-        const T xj = pstep(z, g, j, step);
-        xbar[j] = xj;
-        const double zj = (double)z[j];
-        const double ej = (double)xj - zj;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
-        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-        if (hx) {
-            const T xn = pstep(z, g, j + 1, step);
-            const double zn = (double)z[j + 1];
-            a0 = (double)xn - (double)xj;
-            b0 = zn - zj;
-            d0 = ((double)xn - zn) - ej;
-        }
-        if (hy) {
-            const T xn = pstep(z, g, j + sy, step);
-            const double zn = (double)z[j + sy];
-            a1 = (double)xn - (double)xj;
-            b1 = zn - zj;
-            d1 = ((double)xn - zn) - ej;
-        }
-        if (hz) {
-            const T xn = pstep(z, g, j + sz, step);
-            const double zn = (double)z[j + sz];
-            a2 = (double)xn - (double)xj;
-            b2 = zn - zj;
-            d2 = ((double)xn - zn) - ej;
-        }
-        const double gj = (double)g[j];
-        red[0] = ej * ej;
-        red[1] = -gj * ej;
-        red[2] = huber(sqrt(a0 * a0 + a1 * a1 + a2 * a2), tau);
-        red[3] = huber_bregman(a0, a1, a2, b0, b1, b2, d0, d1, d2, tau);
-        if (gm_step > 0.0) {
-            const double p = zj - fmax(zj - gm_step * gj, 0.0);
-            red[4] = p * p;
+        const bool hx = ix + 1 < nx, hy = iy + 1 < ny;
+        size_t j = (size_t)ix + sy * iy + sz * z0;
+        T xj = pstep(zv, g, j, step), zj = zv[j];
+        for (int z = z0; z < z1; ++z, j += sz) {
+            const bool hz = z + 1 < nz;
+            const T gj = g[j];
+            const T xxp = hx ? pstep(zv, g, j + 1, step) : xj;
+            const T zxp = hx ? zv[j + 1] : zj;
+            const T xyp = hy ? pstep(zv, g, j + sy, step) : xj;
+            const T zyp = hy ? zv[j + sy] : zj;
+            const T xzp = hz ? pstep(zv, g, j + sz, step) : xj;
+            const T zzp = hz ? zv[j + sz] : zj;
+            xbar[j] = xj;
+            const double ed = (double)xj - (double)zj;
+            red[0] += ed * ed;
+            red[1] -= (double)gj * ed;
+            const T a0 = xxp - xj, a1 = xyp - xj, a2 = xzp - xj;
+            const T b0 = zxp - zj, b1 = zyp - zj, b2 = zzp - zj;
+            const T ej = xj - zj;
+            const T d0 = (xxp - zxp) - ej, d1 = (xyp - zyp) - ej, d2 = (xzp - zzp) - ej;
+            red[2] += (double)huber_c<T>(a0 * a0 + a1 * a1 + a2 * a2, ct, itau);
+            red[3] += (double)huber_bregman<T>(a0, a1, a2, b0, b1, b2, d0, d1, d2, ct, itau);
+            if (gm_step > 0.0) {
+                const double zd = (double)zj;
+                const double p = zd - fmax(zd - gm_step * (double)gj, 0.0);
+                red[4] += p * p;
+            }
+            xj = xzp;  // the next plane's own values
+            zj = zzp;
         }
     }
     const int slots[5] = {S_XD2, S_GD, S_TVB, S_BRB, S_GM2};
@@ -313,6 +359,11 @@ __global__ void combine_phi_kernel(const double *r2, const double *tv, double al
         *out = 0.5 * (*r2) + alpha * (*tv);
 }
 
+dim3 voxel_grid(int nx, int ny, int nz)
+{
+    return dim3((nx + VX - 1) / VX, (ny + VY - 1) / VY, (nz + VZ - 1) / VZ);
+}
+
 }  // namespace
 
 int elementwise_blocks(int64_t n)
@@ -325,8 +376,8 @@ int elementwise_blocks(int64_t n)
 
 int max_reduce_blocks_vol(int nx, int ny, int nz)
 {
-    const int64_t N = (int64_t)nx * ny * nz;
-    return (int)((N + VB - 1) / VB);
+    const dim3 gr = voxel_grid(nx, ny, nz);
+    return (int)(gr.x * gr.y * gr.z);
 }
 
 template <typename T>
@@ -334,10 +385,10 @@ hipError_t launch_tv(int nx, int ny, int nz, double tau, double alpha, const T *
                      const T *gin, T *gout, double *partials, int pstride, hipStream_t st,
                      int *nblocks)
 {
-    const int nb = max_reduce_blocks_vol(nx, ny, nz);
+    const dim3 gr = voxel_grid(nx, ny, nz);
     if (nblocks)
-        *nblocks = nb;
-    hipLaunchKernelGGL((tv_kernel<T>), dim3(nb), dim3(VB), 0, st, nx, ny, nz, tau, alpha, y, xref,
+        *nblocks = (int)(gr.x * gr.y * gr.z);
+    hipLaunchKernelGGL((tv_kernel<T>), gr, dim3(VX, VY), 0, st, nx, ny, nz, tau, alpha, y, xref,
                        gin, gout, partials, pstride);
     return hipGetLastError();
 }
@@ -347,10 +398,10 @@ hipError_t launch_trial(int nx, int ny, int nz, double tau, const T *z, const T 
                         double gm_step, T *xbar, double *partials, int pstride, hipStream_t st,
                         int *nblocks)
 {
-    const int nb = max_reduce_blocks_vol(nx, ny, nz);
+    const dim3 gr = voxel_grid(nx, ny, nz);
     if (nblocks)
-        *nblocks = nb;
-    hipLaunchKernelGGL((trial_kernel<T>), dim3(nb), dim3(VB), 0, st, nx, ny, nz, tau, z, g, step,
+        *nblocks = (int)(gr.x * gr.y * gr.z);
+    hipLaunchKernelGGL((trial_kernel<T>), gr, dim3(VX, VY), 0, st, nx, ny, nz, tau, z, g, step,
                        gm_step, xbar, partials, pstride);
     return hipGetLastError();
 }

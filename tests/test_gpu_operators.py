@@ -146,7 +146,9 @@ def test_tv_matches_oracle(shape, tau, kind, prec):
     g, T = tv.tv_grad(to_dev(x, prec), tau)
     torch.cuda.synchronize()
     T = float(T.item())
-    assert abs(T - T_ref) <= 1e-12 * max(T_ref, 1e-300) + 1e-300
+    # FP32 path: per-voxel Phi in float (a few ulps each), summed in double
+    tol_T = 1e-12 if prec == tv.F64 else 1e-6
+    assert abs(T - T_ref) <= tol_T * max(T_ref, 1e-300) + 1e-300
     got = g.cpu().double().numpy()
     scale = max(np.max(np.abs(g_ref)), 1e-300)
     tol = 1e-12 if prec == tv.F64 else 2e-6
@@ -173,8 +175,9 @@ def test_objective_grad_matches_oracle(name, prec):
         assert abs(f - f_ref) <= 1e-12 * f_ref
         assert np.max(np.abs(got - g_ref)) <= 1e-11 * scale
     else:
-        # the residual is stored in FP32 before the backprojection
-        assert abs(f - f_ref) <= 1e-9 * f_ref
+        # the residual is stored in FP32 before the backprojection; per-voxel
+        # TV terms are float, summed in double
+        assert abs(f - f_ref) <= 1e-7 * f_ref
         assert np.max(np.abs(got - g_ref)) <= 1e-6 * scale
 
 
@@ -214,5 +217,5 @@ def test_cone256_tv_full(big):
     T_ref, g_ref = oracle.tv(x, big.tau)
     g, T = tv.tv_grad(to_dev(x, tv.F32), big.tau)
     torch.cuda.synchronize()
-    assert abs(float(T.item()) - T_ref) <= 1e-12 * T_ref
+    assert abs(float(T.item()) - T_ref) <= 1e-6 * T_ref
     assert np.max(np.abs(g.cpu().double().numpy() - g_ref)) <= 2e-6 * np.max(np.abs(g_ref))
