@@ -173,6 +173,36 @@ tvreg_status tvreg_solve(const tvreg_geometry *geom, const void *b_dev,
                          void *workspace_dev, size_t workspace_bytes, tvreg_solve_info *info,
                          void *stream);
 
+/* Bytes of device workspace tvreg_solve_batched needs for these n geometries. */
+size_t tvreg_solve_batched_workspace_bytes(int32_t n, const tvreg_geometry *const *geoms);
+
+/*
+ * n independent GP (eq. 6) or UPN (Alg. 3) solves run together: problem i has
+ * its own geometry geoms[i], data b_dev[i] (m_i values of T), parameters
+ * params[i] (alpha, eps, L_bar, ... each its own) and start / result
+ * x_inout_dev[i] (N_i values of T).  The problems take exactly the steps and
+ * decisions tvreg_solve takes for each of them alone (same kernels, same
+ * partial-sum order, same double arithmetic for the line search of Alg. 2,
+ * the mu estimate of eq. 9 and the stop test), so every result is the one
+ * tvreg_solve returns; only the launch structure differs: one line-search
+ * trial of every running problem is one round of grouped launches plus a
+ * device-side control step, captured once as a HIP graph and replayed; the
+ * host reads one running-problem count every `poll_rounds` rounds (<= 0
+ * selects 8).
+ * All geometries share one precision and one device.  GPBB is not batched
+ * (TVREG_EINVAL); the history arrays of params are ignored.  geoms, b_dev,
+ * params, x_inout_dev and infos are host arrays of n entries; b_dev and
+ * x_inout_dev entries are device pointers.  infos[i] is written on the host,
+ * its stop_reason holds problem i's status.  Returns TVREG_OK when every
+ * problem converged, else TVREG_ESTALL if one stalled, else TVREG_ENOTCONV,
+ * or a negative error.  Synchronises `stream`.
+ */
+tvreg_status tvreg_solve_batched(int32_t n, const tvreg_geometry *const *geoms,
+                                 const void *const *b_dev, const tvreg_solve_params *params,
+                                 void *const *x_inout_dev, void *workspace_dev,
+                                 size_t workspace_bytes, int32_t poll_rounds,
+                                 tvreg_solve_info *infos, void *stream);
+
 /*
  * Opt-in instrumentation of tvreg_solve: when enabled, every kernel launch of
  * a solve is bracketed by HIP events on the solve's stream and the elapsed

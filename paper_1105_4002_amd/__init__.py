@@ -59,8 +59,9 @@ class _SolveInfo(ctypes.Structure):
 EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
            "tvreg_backproject", "tvreg_tv_workspace_bytes", "tvreg_tv_grad",
            "tvreg_objective_workspace_bytes", "tvreg_objective_grad",
-           "tvreg_solve_workspace_bytes", "tvreg_solve", "tvreg_profile_enable",
-           "tvreg_profile_reset", "tvreg_profile_get", "tvreg_last_error", "tvreg_version")
+           "tvreg_solve_workspace_bytes", "tvreg_solve", "tvreg_solve_batched_workspace_bytes",
+           "tvreg_solve_batched", "tvreg_profile_enable", "tvreg_profile_reset",
+           "tvreg_profile_get", "tvreg_last_error", "tvreg_version")
 
 KERNELS = {"project": 0, "backproject": 1, "tv": 2, "trial": 3, "extrapolate": 4,
            "transpose": 5}
@@ -96,6 +97,12 @@ def _load():
     L.tvreg_solve.argtypes = [vp, vp, ctypes.POINTER(_SolveParams), vp, vp, sz,
                               ctypes.POINTER(_SolveInfo), vp]
     L.tvreg_solve.restype = st
+    L.tvreg_solve_batched_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(vp)]
+    L.tvreg_solve_batched_workspace_bytes.restype = sz
+    L.tvreg_solve_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(_SolveParams), ctypes.POINTER(vp), vp, sz,
+                                      ctypes.c_int32, ctypes.POINTER(_SolveInfo), vp]
+    L.tvreg_solve_batched.restype = st
     L.tvreg_profile_enable.argtypes = [ctypes.c_int32]
     L.tvreg_profile_enable.restype = None
     L.tvreg_profile_reset.argtypes = []
@@ -268,6 +275,63 @@ def solve(geom: Geometry, b: torch.Tensor, method: int = UPN, alpha: float = 1e-
     n = min(hl, out["iters"])
     hist = {"phi": list(hists[0])[:n], "gm": list(hists[1])[:n], "L": list(hists[2])[:n]}
     return x, out, hist
+
+
+def _handles(geoms):
+    return (ctypes.c_void_p * len(geoms))(*[g.handle.value for g in geoms])
+
+
+def solve_batched_workspace(geoms, device="cuda") -> torch.Tensor:
+    nb = _lib.tvreg_solve_batched_workspace_bytes(len(geoms), _handles(geoms))
+    if nb == 0:
+        raise ValueError("geometries must be non-empty and share one precision")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+_BATCH_DEFAULTS = dict(method=UPN, alpha=1e-2, tau=1e-4, eps=1e-6, stop_mode=0, max_iter=10000,
+                       L_bar=1.0, mu_bar=0.0, rho_L=2.0, max_trials=60)
+
+
+def solve_batched(geoms, bs, params, x0s=None, poll_rounds: int = 8,
+                  workspace: Optional[torch.Tensor] = None):
+    """Solves len(geoms) GP / UPN problems together (tvreg_solve_batched).
+
+    params: one dict per problem with any of the keys method, alpha, tau,
+    eps, stop_mode, max_iter, L_bar, mu_bar, rho_L, max_trials (defaults as
+    in solve()).  Returns (list of x, list of info dicts, batch status)."""
+    n = len(geoms)
+    if not (len(bs) == n and len(params) == n):
+        raise ValueError("geoms, bs and params must have one entry per problem")
+    ps = []
+    for q in params:
+        unknown = set(q) - set(_BATCH_DEFAULTS)
+        if unknown:
+            raise ValueError(f"unknown batched solve parameters {sorted(unknown)}")
+        ps.append({**_BATCH_DEFAULTS, **q})
+    xs = []
+    for i, g in enumerate(geoms):
+        if x0s is None:
+            xs.append(torch.zeros(g.vol_shape, dtype=g.dtype, device=bs[i].device))
+        else:
+            xs.append(x0s[i].detach().clone().contiguous())
+    ws = workspace if workspace is not None else solve_batched_workspace(geoms, bs[0].device)
+    cp = (_SolveParams * n)()
+    for i, q in enumerate(ps):
+        cp[i] = _SolveParams(int(q["method"]), float(q["alpha"]), float(q["tau"]),
+                             float(q["eps"]), int(q["stop_mode"]), int(q["max_iter"]),
+                             float(q["L_bar"]), float(q["mu_bar"]), float(q["rho_L"]), 2, 0.1,
+                             0.95, int(q["max_trials"]), None, None, None, 0)
+    bp = (ctypes.c_void_p * n)(*[_ptr(bs[i], g.dtype, g.m, f"b[{i}]").value
+                                  for i, g in enumerate(geoms)])
+    xp = (ctypes.c_void_p * n)(*[_ptr(xs[i], g.dtype, g.N, f"x[{i}]").value
+                                  for i, g in enumerate(geoms)])
+    infos = (_SolveInfo * n)()
+    status = _check(_lib.tvreg_solve_batched(n, _handles(geoms), bp, cp, xp,
+                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                             int(poll_rounds), infos, _stream(bs[0])),
+                    "tvreg_solve_batched")
+    out = [{k: getattr(infos[i], k) for k, _ in _SolveInfo._fields_} for i in range(n)]
+    return xs, out, status
 
 
 def profile_enable(on: bool = True) -> None:

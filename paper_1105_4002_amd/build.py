@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build", "tvreg")
 LIB_PATH = os.path.join(PKG, "libtvreg.so")
-SOURCES = ["project.hip", "backproject.hip", "stencil.hip", "api.hip"]
+SOURCES = ["project.hip", "backproject.hip", "stencil.hip", "batch.hip", "api.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

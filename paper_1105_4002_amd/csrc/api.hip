@@ -16,16 +16,15 @@
 #include <string>
 #include <vector>
 
-#include "tvreg.h"
-#include "tvreg_internal.hpp"
+#include "host.hpp"
 
 using namespace tvr;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-tvreg_status fail(tvreg_status s, const char *fmt, ...)
+tvreg_status tvr::fail(tvreg_status s, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -36,57 +35,28 @@ tvreg_status fail(tvreg_status s, const char *fmt, ...)
     return s;
 }
 
-#define TVR_HIP(call)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail(TVREG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
-    } while (0)
+void tvr::clear_error() { g_err.clear(); }
 
-#define TVR_TRY(expr)                                                                          \
-    do {                                                                                       \
-        tvreg_status s_ = (expr);                                                              \
-        if (s_ < 0)                                                                            \
-            return s_;                                                                         \
-    } while (0)
-
-// Makes the geometry's device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) {
-            ok = false;
-            return;
-        }
-        if (prev != dev && hipSetDevice(dev) != hipSuccess)
-            ok = false;
-    }
-    ~DeviceGuard()
-    {
-        int cur;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
-            (void)hipSetDevice(prev);
-    }
-};
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-}  // namespace
-
-struct tvreg_geometry {
-    tvreg_geometry_desc desc;
-    std::vector<double> angles;
-    tvreg_precision prec;
-    int device;
-    GeomDev g;
-    void *dev_tables;
-    int64_t N, m;
-    int pstride;  // partial-sum capacity per slot
-};
-
-static size_t elem_size(tvreg_precision p) { return p == TVREG_F64 ? 8 : 4; }
+tvreg_status tvr::check_solve_params(const tvreg_solve_params *p)
+{
+    if (p->method != TVREG_GP && p->method != TVREG_GPBB && p->method != TVREG_UPN)
+        return fail(TVREG_EINVAL, "unknown method %d", (int)p->method);
+    if (!(p->tau > 0) || !isfinite(p->tau) || !(p->alpha >= 0) || !isfinite(p->alpha))
+        return fail(TVREG_EINVAL, "tau must be > 0 and alpha >= 0");
+    if (!(p->eps >= 0) || p->max_iter < 1 || !(p->L_bar > 0) || !(p->rho_L > 1) ||
+        p->max_trials < 1)
+        return fail(TVREG_EINVAL, "need eps >= 0, max_iter >= 1, L_bar > 0, rho_L > 1, "
+                                  "max_trials >= 1");
+    if (p->stop_mode != 0 && p->stop_mode != 1)
+        return fail(TVREG_EINVAL, "stop_mode must be 0 or 1");
+    if (p->method == TVREG_GPBB &&
+        (p->gpbb_K < 0 || p->gpbb_K > 16 || !(p->gpbb_beta0 > 0 && p->gpbb_beta0 < 1) ||
+         !(p->gpbb_sigma >= 0)))
+        return fail(TVREG_EINVAL, "GPBB needs 0 <= K <= 16, 0 < beta0 < 1, sigma >= 0");
+    if (p->hist_len < 0)
+        return fail(TVREG_EINVAL, "hist_len < 0");
+    return TVREG_OK;
+}
 
 extern "C" const char *tvreg_last_error(void) { return g_err.c_str(); }
 
@@ -289,7 +259,6 @@ extern "C" tvreg_status tvreg_backproject(const tvreg_geometry *G, const void *r
     return TVREG_OK;
 }
 
-static size_t partial_bytes(int pstride) { return sizeof(double) * (size_t)S_COUNT * pstride; }
 
 extern "C" size_t tvreg_tv_workspace_bytes(int32_t nx, int32_t ny, int32_t nz)
 {
@@ -880,22 +849,7 @@ extern "C" tvreg_status tvreg_solve(const tvreg_geometry *G, const void *b,
     g_err.clear();
     if (!G || !b || !p || !x || !info)
         return fail(TVREG_EINVAL, "NULL argument");
-    if (p->method != TVREG_GP && p->method != TVREG_GPBB && p->method != TVREG_UPN)
-        return fail(TVREG_EINVAL, "unknown method %d", (int)p->method);
-    if (!(p->tau > 0) || !isfinite(p->tau) || !(p->alpha >= 0) || !isfinite(p->alpha))
-        return fail(TVREG_EINVAL, "tau must be > 0 and alpha >= 0");
-    if (!(p->eps >= 0) || p->max_iter < 1 || !(p->L_bar > 0) || !(p->rho_L > 1) ||
-        p->max_trials < 1)
-        return fail(TVREG_EINVAL, "need eps >= 0, max_iter >= 1, L_bar > 0, rho_L > 1, "
-                                  "max_trials >= 1");
-    if (p->stop_mode != 0 && p->stop_mode != 1)
-        return fail(TVREG_EINVAL, "stop_mode must be 0 or 1");
-    if (p->method == TVREG_GPBB &&
-        (p->gpbb_K < 0 || p->gpbb_K > 16 || !(p->gpbb_beta0 > 0 && p->gpbb_beta0 < 1) ||
-         !(p->gpbb_sigma >= 0)))
-        return fail(TVREG_EINVAL, "GPBB needs 0 <= K <= 16, 0 < beta0 < 1, sigma >= 0");
-    if (p->hist_len < 0)
-        return fail(TVREG_EINVAL, "hist_len < 0");
+    TVR_TRY(check_solve_params(p));
     if (!ws || ws_bytes < solve_layout(G).total)
         return fail(TVREG_ENOMEM, "workspace of %zu bytes needed", solve_layout(G).total);
     DeviceGuard dg(G->device);

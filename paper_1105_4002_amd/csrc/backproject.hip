@@ -19,6 +19,7 @@
 // gets the exact interval arithmetic, selected to zero where it is empty.
 // A view whose footprint exceeds the tile (unusual geometries) takes the
 // generic arithmetic with global loads.
+#include "reduce.hpp"
 #include "tvreg_internal.hpp"
 
 namespace tvr {
@@ -264,17 +265,16 @@ __device__ __forceinline__ void gather_cone_tile(const GeomDev &g, const Tile &T
     }
 }
 
+// One block: BP_TX x BP_TY voxel columns, CZ voxels deep, block (bx, by, bz).
 template <typename T, bool CONE, int CZ>
-__global__ __launch_bounds__(BP_THREADS) void backproject_kernel(GeomDev g,
-                                                                const T *__restrict__ r,
-                                                                T *__restrict__ out)
+__device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__restrict__ r,
+                                                  T *__restrict__ out, int bx, int by, int bz,
+                                                  Tile &tile)
 {
-    __shared__ Tile tile;
-
     const int tid = threadIdx.x;
-    const int ix = blockIdx.x * BP_TX + (tid % BP_TX);
-    const int iy = blockIdx.y * BP_TY + (tid / BP_TX);
-    const int iz0 = blockIdx.z * CZ;
+    const int ix = bx * BP_TX + (tid % BP_TX);
+    const int iy = by * BP_TY + (tid / BP_TX);
+    const int iz0 = bz * CZ;
     // threads past the volume edge still stage data and meet every barrier
     const bool active = ix < g.nx && iy < g.ny;
 
@@ -286,8 +286,8 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_kernel(GeomDev g,
     const double X0 = -g.hx + (double)ix, X1 = X0 + 1.0;
     const double Y0 = -g.hy + (double)iy, Y1 = Y0 + 1.0;
     // the block's box
-    const double bX0 = -g.hx + (double)(blockIdx.x * BP_TX);
-    const double bY0 = -g.hy + (double)(blockIdx.y * BP_TY);
+    const double bX0 = -g.hx + (double)(bx * BP_TX);
+    const double bY0 = -g.hy + (double)(by * BP_TY);
     const double bZ0 = -g.hz + (double)iz0;
     const double bX1 = fmin(bX0 + BP_TX, g.hx), bY1 = fmin(bY0 + BP_TY, g.hy);
     const double bZ1 = fmin(bZ0 + CZ, g.hz);
@@ -362,7 +362,55 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_kernel(GeomDev g,
     }
 }
 
+template <typename T, bool CONE, int CZ>
+__global__ __launch_bounds__(BP_THREADS) void backproject_kernel(GeomDev g,
+                                                                const T *__restrict__ r,
+                                                                T *__restrict__ out)
+{
+    __shared__ Tile tile;
+    backproject_block<T, CONE, CZ>(g, r, out, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+}
+
+// Batched: G = A^T RY for every problem whose gradient is due this round.
+template <typename T>
+__global__ __launch_bounds__(BP_THREADS) void backproject_grouped(BatchProblem<T> *probs,
+                                                                 const int *offs, int n)
+{
+    __shared__ Tile tile;
+    const int p = find_problem(offs, n, blockIdx.x);
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING || !P.need_grad)
+        return;
+    const int local = blockIdx.x - offs[p];
+    const int gx = (P.g.nx + BP_TX - 1) / BP_TX, gy = (P.g.ny + BP_TY - 1) / BP_TY;
+    const int bx = local % gx, by = (local / gx) % gy, bz = local / (gx * gy);
+    if (P.g.cone)
+        backproject_block<T, true, BP_CZ>(P.g, P.RY, P.G, bx, by, bz, tile);
+    else
+        backproject_block<T, false, BP_CZ>(P.g, P.RY, P.G, bx, by, bz, tile);
+}
+
 }  // namespace
+
+int backproject_blocks(const GeomDev &g)
+{
+    return ((g.nx + BP_TX - 1) / BP_TX) * ((g.ny + BP_TY - 1) / BP_TY) *
+           ((g.nz + BP_CZ - 1) / BP_CZ);
+}
+
+template <typename T>
+hipError_t launch_backproject_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                                      hipStream_t st)
+{
+    hipLaunchKernelGGL((backproject_grouped<T>), dim3(blocks), dim3(BP_THREADS), 0, st, probs,
+                       offs, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_backproject_grouped<float>(BatchProblem<float> *, const int *, int,
+                                                      int, hipStream_t);
+template hipError_t launch_backproject_grouped<double>(BatchProblem<double> *, const int *, int,
+                                                       int, hipStream_t);
 
 template <typename T>
 hipError_t launch_backproject(const GeomDev &g, const T *r, T *out, hipStream_t st)

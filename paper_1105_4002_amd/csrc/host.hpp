@@ -1,0 +1,73 @@
+// Host-side helpers shared by the C-ABI translation units: the geometry
+// handle, error recording, device selection and workspace arithmetic.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "tvreg.h"
+#include "tvreg_internal.hpp"
+
+// The opaque handle of the C ABI.
+struct tvreg_geometry {
+    tvreg_geometry_desc desc;
+    std::vector<double> angles;
+    tvreg_precision prec;
+    int device;
+    tvr::GeomDev g;
+    void *dev_tables;
+    int64_t N, m;
+    int pstride;  // partial-sum capacity per slot
+};
+
+namespace tvr {
+
+// Records the message returned by tvreg_last_error() and passes s through.
+tvreg_status fail(tvreg_status s, const char *fmt, ...);
+void clear_error();
+
+// Argument checks shared by tvreg_solve and tvreg_solve_batched.
+tvreg_status check_solve_params(const tvreg_solve_params *p);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline size_t elem_size(tvreg_precision p) { return p == TVREG_F64 ? 8 : 4; }
+inline size_t partial_bytes(int pstride) { return sizeof(double) * (size_t)S_COUNT * pstride; }
+
+// Makes a device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            ok = false;
+            return;
+        }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess)
+            ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+            (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace tvr
+
+#define TVR_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return tvr::fail(TVREG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+#define TVR_TRY(expr)                                                                          \
+    do {                                                                                       \
+        tvreg_status s_ = (expr);                                                              \
+        if (s_ < 0)                                                                            \
+            return s_;                                                                         \
+    } while (0)

@@ -108,18 +108,16 @@ __device__ __forceinline__ double ray_walk(const GeomDev &g, const T *__restrict
     return acc;
 }
 
+// One block: PJ_TX detector columns x PJ_TY rows of view v.
 template <typename T, bool CONE>
-__global__ __launch_bounds__(PJ_TX *PJ_TY) void project_kernel(GeomDev g, const T *__restrict__ x,
-                                                              const T *__restrict__ xt,
-                                                              const T *__restrict__ b,
-                                                              T *__restrict__ out,
-                                                              const T *__restrict__ rref,
-                                                              double *__restrict__ partials,
-                                                              int pstride)
+__device__ __forceinline__ void project_block(const GeomDev &g, const T *__restrict__ x,
+                                              const T *__restrict__ xt, const T *__restrict__ b,
+                                              T *__restrict__ out, const T *__restrict__ rref,
+                                              double *__restrict__ partials, int pstride,
+                                              int bx, int by, int v, int bid)
 {
-    const int col = blockIdx.x * PJ_TX + threadIdx.x;
-    const int row = blockIdx.y * PJ_TY + threadIdx.y;
-    const int v = blockIdx.z;
+    const int col = bx * PJ_TX + threadIdx.x;
+    const int row = by * PJ_TY + threadIdx.y;
     double red[2] = {0.0, 0.0};
     if (col < g.cols && row < g.rows) {
         const ColEntry ce = g.col[(size_t)v * g.cols + col];
@@ -143,11 +141,59 @@ __global__ __launch_bounds__(PJ_TX *PJ_TY) void project_kernel(GeomDev g, const 
     }
     if (partials) {
         const int slots[2] = {S_R2, S_RD2};
-        block_reduce_store<2>(red, partials, pstride, slots);
+        block_reduce_store<2>(red, partials, pstride, slots, bid);
     }
 }
 
+template <typename T, bool CONE>
+__global__ __launch_bounds__(PJ_TX *PJ_TY) void project_kernel(GeomDev g, const T *__restrict__ x,
+                                                              const T *__restrict__ xt,
+                                                              const T *__restrict__ b,
+                                                              T *__restrict__ out,
+                                                              const T *__restrict__ rref,
+                                                              double *__restrict__ partials,
+                                                              int pstride)
+{
+    project_block<T, CONE>(g, x, xt, b, out, rref, partials, pstride, blockIdx.x, blockIdx.y,
+                           blockIdx.z, block_linear_id());
+}
+
+// Batched: the trial points XB of every running problem (residual against
+// b, Bregman data term against RY).
+template <typename T>
+__global__ __launch_bounds__(PJ_TX *PJ_TY) void project_grouped(BatchProblem<T> *probs,
+                                                               const int *offs, int n)
+{
+    const int p = find_problem(offs, n, blockIdx.x);
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING)
+        return;
+    const int local = blockIdx.x - offs[p];
+    const int gx = (P.g.cols + PJ_TX - 1) / PJ_TX, gy = (P.g.rows + PJ_TY - 1) / PJ_TY;
+    const int bx = local % gx, by = (local / gx) % gy, v = local / (gx * gy);
+    if (P.g.cone)
+        project_block<T, true>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx, by, v,
+                               local);
+    else
+        project_block<T, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx, by, v,
+                                local);
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                                  hipStream_t st)
+{
+    hipLaunchKernelGGL((project_grouped<T>), dim3(blocks), dim3(PJ_TX, PJ_TY), 0, st, probs,
+                       offs, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_project_grouped<float>(BatchProblem<float> *, const int *, int, int,
+                                                  hipStream_t);
+template hipError_t launch_project_grouped<double>(BatchProblem<double> *, const int *, int, int,
+                                                   hipStream_t);
 
 template <typename T>
 hipError_t launch_project(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,

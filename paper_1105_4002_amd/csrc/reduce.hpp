@@ -25,10 +25,10 @@ __device__ __forceinline__ int thread_linear_id()
     return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
 }
 
-// Reduces v[0..NQ) over the block; thread 0 writes partials[slot[q] * pstride + block].
+// Reduces v[0..NQ) over the block; thread 0 writes partials[slot[q] * pstride + bid].
 template <int NQ>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NQ], double *partials,
-                                                   int pstride, const int (&slot)[NQ])
+                                                   int pstride, const int (&slot)[NQ], int bid)
 {
     __shared__ double sh[NQ][16];
     const int tid = thread_linear_id();
@@ -43,7 +43,6 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NQ], double *part
     __syncthreads();
     if (tid == 0) {
         const int nw = (nthreads + 63) >> 6;
-        const int bid = block_linear_id();
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             double s = 0.0;
@@ -52,6 +51,28 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NQ], double *part
             partials[(size_t)slot[q] * pstride + bid] = s;
         }
     }
+}
+
+template <int NQ>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NQ], double *partials,
+                                                   int pstride, const int (&slot)[NQ])
+{
+    block_reduce_store<NQ>(v, partials, pstride, slot, block_linear_id());
+}
+
+// Problem owning block b of a grouped launch: offs[p] is the first block of
+// problem p (offs[0] = 0, increasing).
+__device__ __forceinline__ int find_problem(const int *offs, int n, int b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 }  // namespace tvr

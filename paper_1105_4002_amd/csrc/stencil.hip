@@ -98,16 +98,15 @@ __device__ __forceinline__ C huber_bregman(C a0, C a1, C a2, C b0, C b1, C b2, C
 // gout = (gin ? gin : 0) + alpha grad T(y); with partials also the sums
 // T(y) and, with xref, Bregman_T(xref, y) and |xref - y|^2.
 template <typename T>
-__global__ __launch_bounds__(VX *VY) void tv_kernel(int nx, int ny, int nz, double tau,
-                                                    double alpha, const T *__restrict__ y,
-                                                    const T *__restrict__ xref,
-                                                    const T *__restrict__ gin,
-                                                    T *__restrict__ gout,
-                                                    double *__restrict__ partials, int pstride)
+__device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, double alpha,
+                                         const T *__restrict__ y, const T *__restrict__ xref,
+                                         const T *__restrict__ gin, T *__restrict__ gout,
+                                         double *__restrict__ partials, int pstride, int bx,
+                                         int by, int bz, int bid)
 {
-    const int ix = blockIdx.x * VX + threadIdx.x;
-    const int iy = blockIdx.y * VY + threadIdx.y;
-    const int z0 = blockIdx.z * VZ;
+    const int ix = bx * VX + threadIdx.x;
+    const int iy = by * VY + threadIdx.y;
+    const int z0 = bz * VZ;
     const int z1 = min(z0 + VZ, nz);
     double red[3] = {0.0, 0.0, 0.0};
     if (ix < nx && iy < ny) {
@@ -184,8 +183,47 @@ __global__ __launch_bounds__(VX *VY) void tv_kernel(int nx, int ny, int nz, doub
     }
     if (partials) {
         const int slots[3] = {S_TVY, S_BRY, S_XY2};
-        block_reduce_store<3>(red, partials, pstride, slots);
+        block_reduce_store<3>(red, partials, pstride, slots, bid);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(VX *VY) void tv_kernel(int nx, int ny, int nz, double tau,
+                                                    double alpha, const T *__restrict__ y,
+                                                    const T *__restrict__ xref,
+                                                    const T *__restrict__ gin,
+                                                    T *__restrict__ gout,
+                                                    double *__restrict__ partials, int pstride)
+{
+    tv_block<T>(nx, ny, nz, tau, alpha, y, xref, gin, gout, partials, pstride, blockIdx.x,
+                blockIdx.y, blockIdx.z, block_linear_id());
+}
+
+// local block -> (bx, by, bz) of a voxel grid
+__device__ __forceinline__ void voxel_block_coords(int local, int nx, int ny, int &bx, int &by,
+                                                   int &bz)
+{
+    const int gx = (nx + VX - 1) / VX, gy = (ny + VY - 1) / VY;
+    bx = local % gx;
+    by = (local / gx) % gy;
+    bz = local / (gx * gy);
+}
+
+// Batched gradient assembly G += alpha grad T(Y), with the Bregman terms
+// against X once Y has moved away from X.
+template <typename T>
+__global__ __launch_bounds__(VX *VY) void tv_grouped(BatchProblem<T> *probs, const int *offs,
+                                                     int n)
+{
+    const int p = find_problem(offs, n, blockIdx.x);
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING || !P.need_grad)
+        return;
+    const int local = blockIdx.x - offs[p];
+    int bx, by, bz;
+    voxel_block_coords(local, P.g.nx, P.g.ny, bx, by, bz);
+    tv_block<T>(P.g.nx, P.g.ny, P.g.nz, P.tau, P.alpha, P.Y, P.distinct ? P.X : nullptr, P.G,
+                P.G, P.part, P.pstride, bx, by, bz, local);
 }
 
 template <typename T>
@@ -199,16 +237,15 @@ __device__ __forceinline__ T pstep(const T *__restrict__ z, const T *__restrict_
 // g^T (z - xbar), T(xbar), Bregman_T(xbar, z) and, for gm_step > 0,
 // |z - P_Q(z - gm_step g)|^2 (the GPBB gradient map).
 template <typename T>
-__global__ __launch_bounds__(VX *VY) void trial_kernel(int nx, int ny, int nz, double tau,
-                                                       const T *__restrict__ zv,
-                                                       const T *__restrict__ g, double step,
-                                                       double gm_step, T *__restrict__ xbar,
-                                                       double *__restrict__ partials,
-                                                       int pstride)
+__device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
+                                            const T *__restrict__ zv, const T *__restrict__ g,
+                                            double step, double gm_step, T *__restrict__ xbar,
+                                            double *__restrict__ partials, int pstride, int bx,
+                                            int by, int bz, int bid)
 {
-    const int ix = blockIdx.x * VX + threadIdx.x;
-    const int iy = blockIdx.y * VY + threadIdx.y;
-    const int z0 = blockIdx.z * VZ;
+    const int ix = bx * VX + threadIdx.x;
+    const int iy = by * VY + threadIdx.y;
+    const int z0 = bz * VZ;
     const int z1 = min(z0 + VZ, nz);
     double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (ix < nx && iy < ny) {
@@ -246,24 +283,60 @@ __global__ __launch_bounds__(VX *VY) void trial_kernel(int nx, int ny, int nz, d
         }
     }
     const int slots[5] = {S_XD2, S_GD, S_TVB, S_BRB, S_GM2};
-    block_reduce_store<5>(red, partials, pstride, slots);
+    block_reduce_store<5>(red, partials, pstride, slots, bid);
+}
+
+template <typename T>
+__global__ __launch_bounds__(VX *VY) void trial_kernel(int nx, int ny, int nz, double tau,
+                                                       const T *__restrict__ zv,
+                                                       const T *__restrict__ g, double step,
+                                                       double gm_step, T *__restrict__ xbar,
+                                                       double *__restrict__ partials,
+                                                       int pstride)
+{
+    trial_block<T>(nx, ny, nz, tau, zv, g, step, gm_step, xbar, partials, pstride, blockIdx.x,
+                   blockIdx.y, blockIdx.z, block_linear_id());
+}
+
+// Batched trial XB = P_Q(Y - G / L) of every running problem.
+template <typename T>
+__global__ __launch_bounds__(VX *VY) void trial_grouped(BatchProblem<T> *probs, const int *offs,
+                                                        int n)
+{
+    const int p = find_problem(offs, n, blockIdx.x);
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING)
+        return;
+    const int local = blockIdx.x - offs[p];
+    int bx, by, bz;
+    voxel_block_coords(local, P.g.nx, P.g.ny, bx, by, bz);
+    trial_block<T>(P.g.nx, P.g.ny, P.g.nz, P.tau, P.Y, P.G, 1.0 / P.L, 0.0, P.XB, P.part,
+                   P.pstride, bx, by, bz, local);
 }
 
 constexpr int EW_MAX_BLOCKS = 4096;
+
+__host__ __device__ __forceinline__ int elementwise_blocks_dev(int64_t n)
+{
+    int64_t b = (n + VB - 1) / VB;
+    if (b > EW_MAX_BLOCKS)
+        b = EW_MAX_BLOCKS;
+    return (int)(b < 1 ? 1 : b);
+}
 
 // xt[z][x][y] = x[z][y][x] through a 32 x 32 LDS tile per block (both the
 // read and the write are coalesced); the padding column avoids bank conflicts.
 constexpr int TR = 32;
 
 template <typename T>
-__global__ __launch_bounds__(256) void transpose_xy_kernel(int nx, int ny, const T *__restrict__ x,
-                                                           T *__restrict__ xt)
+__device__ __forceinline__ void transpose_block(int nx, int ny, const T *__restrict__ x,
+                                                T *__restrict__ xt, int gbx, int gby, int z,
+                                                T (&tile)[TR][TR + 1])
 {
-    __shared__ T tile[TR][TR + 1];
     const size_t plane = (size_t)nx * ny;
-    const T *xs = x + (size_t)blockIdx.z * plane;
-    T *xd = xt + (size_t)blockIdx.z * plane;
-    const int bx = blockIdx.x * TR, by = blockIdx.y * TR;
+    const T *xs = x + (size_t)z * plane;
+    T *xd = xt + (size_t)z * plane;
+    const int bx = gbx * TR, by = gby * TR;
     const int tx = threadIdx.x % TR, ty = threadIdx.x / TR;  // 32 x 8 threads
     for (int j = ty; j < TR; j += 8) {
         const int ix = bx + tx, iy = by + j;
@@ -275,6 +348,107 @@ __global__ __launch_bounds__(256) void transpose_xy_kernel(int nx, int ny, const
         const int iy = by + tx, ix = bx + j;
         if (ix < nx && iy < ny)
             xd[(size_t)ix * ny + iy] = tile[tx][j];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_xy_kernel(int nx, int ny, const T *__restrict__ x,
+                                                           T *__restrict__ xt)
+{
+    __shared__ T tile[TR][TR + 1];
+    transpose_block<T>(nx, ny, x, xt, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_grouped(BatchProblem<T> *probs, const int *offs,
+                                                         int n)
+{
+    __shared__ T tile[TR][TR + 1];
+    const int p = find_problem(offs, n, blockIdx.x);
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING)
+        return;
+    const int local = blockIdx.x - offs[p];
+    const int gx = (P.g.nx + TR - 1) / TR, gy = (P.g.ny + TR - 1) / TR;
+    transpose_block<T>(P.g.nx, P.g.ny, P.XB, P.XT, local % gx, (local / gx) % gy,
+                       local / (gx * gy), tile);
+}
+
+// Batched UPN extrapolation after an accepted step (the control kernel has
+// already made X the new iterate and XB the previous one):
+// YB = X + beta (X - XB), RYB = RX + beta (RX - RXB), sum (RYB - RX)^2.
+template <typename T>
+__global__ __launch_bounds__(256) void extrapolate_grouped(BatchProblem<T> *probs,
+                                                           const int *offs, int n)
+{
+    const int p = find_problem(offs, n, blockIdx.x);
+    BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING || !P.ex)
+        return;
+    // the first blocks cover the volume, the rest the data, partitioned
+    // exactly as the single-problem launches do (same partial sums)
+    const int local = blockIdx.x - offs[p];
+    const int nbN = elementwise_blocks_dev(P.N), nbM = P.nb_ew;
+    const double beta = P.beta;
+    if (local < nbN) {
+        for (int64_t i = (int64_t)local * VB + threadIdx.x; i < P.N; i += (int64_t)nbN * VB) {
+            const double a = (double)P.X[i];
+            P.YB[i] = (T)(a + beta * (a - (double)P.XB[i]));
+        }
+        return;  // block-uniform
+    }
+    const int lb = local - nbN;
+    double red[1] = {0.0};
+    for (int64_t k = (int64_t)lb * VB + threadIdx.x; k < P.m; k += (int64_t)nbM * VB) {
+        const double a = (double)P.RX[k];
+        const T yi = (T)(a + beta * (a - (double)P.RXB[k]));
+        P.RYB[k] = yi;
+        const double d = (double)yi - a;
+        red[0] += d * d;
+    }
+    const int slots[1] = {S_RY2};
+    block_reduce_store<1>(red, P.part, P.pstride, slots, lb);
+}
+
+// Batched finaliser: one block per (problem, slot) of the slots the round
+// produced.
+constexpr int NFIN = 10;
+__constant__ const int fin_slots[NFIN] = {S_XD2, S_GD, S_TVB, S_BRB, S_R2, S_RD2,
+                                          S_TVY, S_BRY, S_XY2, S_RY2};
+
+template <typename T>
+__global__ __launch_bounds__(VB) void finalize_grouped(BatchProblem<T> *probs)
+{
+    const int p = blockIdx.x / NFIN, q = blockIdx.x % NFIN;
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING)
+        return;
+    const int slot = fin_slots[q];
+    int count;
+    if (slot == S_R2 || slot == S_RD2)
+        count = P.nb_proj;
+    else if (slot == S_TVY || slot == S_BRY || slot == S_XY2)
+        count = P.need_grad ? P.nb_vox : 0;
+    else if (slot == S_RY2)
+        count = P.ry2_pending ? P.nb_ew : 0;
+    else
+        count = P.nb_vox;
+    if (count == 0)
+        return;
+    const double *src = P.part + (size_t)slot * P.pstride;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += VB)
+        s += src[i];
+    __shared__ double sh[VB / 64];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < VB / 64; ++w)
+            t += sh[w];
+        P.sum[slot] = t;
     }
 }
 
@@ -460,6 +634,64 @@ hipError_t launch_combine_phi(const double *r2, const double *tv, double alpha, 
     hipLaunchKernelGGL(combine_phi_kernel, dim3(1), dim3(64), 0, st, r2, tv, alpha, out);
     return hipGetLastError();
 }
+
+int transpose_blocks(int nx, int ny, int nz)
+{
+    return ((nx + TR - 1) / TR) * ((ny + TR - 1) / TR) * nz;
+}
+
+template <typename T>
+hipError_t launch_tv_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL((tv_grouped<T>), dim3(blocks), dim3(VX, VY), 0, st, probs, offs, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_trial_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL((trial_grouped<T>), dim3(blocks), dim3(VX, VY), 0, st, probs, offs, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transpose_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                                    hipStream_t st)
+{
+    hipLaunchKernelGGL((transpose_grouped<T>), dim3(blocks), dim3(256), 0, st, probs, offs, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_extrapolate_grouped(BatchProblem<T> *probs, const int *offs, int n,
+                                      int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((extrapolate_grouped<T>), dim3(blocks), dim3(VB), 0, st, probs, offs, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_finalize_grouped(BatchProblem<T> *probs, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL((finalize_grouped<T>), dim3(n * NFIN), dim3(VB), 0, st, probs);
+    return hipGetLastError();
+}
+
+#define TVR_INST_GROUPED(T)                                                                      \
+    template hipError_t launch_tv_grouped<T>(BatchProblem<T> *, const int *, int, int,           \
+                                             hipStream_t);                                       \
+    template hipError_t launch_trial_grouped<T>(BatchProblem<T> *, const int *, int, int,        \
+                                                hipStream_t);                                    \
+    template hipError_t launch_transpose_grouped<T>(BatchProblem<T> *, const int *, int, int,    \
+                                                    hipStream_t);                                \
+    template hipError_t launch_extrapolate_grouped<T>(BatchProblem<T> *, const int *, int, int,  \
+                                                      hipStream_t);                              \
+    template hipError_t launch_finalize_grouped<T>(BatchProblem<T> *, int, hipStream_t);
+
+TVR_INST_GROUPED(float)
+TVR_INST_GROUPED(double)
 
 #define TVR_INST(T)                                                                              \
     template hipError_t launch_tv<T>(int, int, int, double, double, const T *, const T *,       \

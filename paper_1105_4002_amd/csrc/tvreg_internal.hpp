@@ -125,5 +125,57 @@ hipError_t launch_combine_phi(const double *r2, const double *tv, double alpha, 
 int project_blocks(const GeomDev &g);
 int max_reduce_blocks_vol(int nx, int ny, int nz);
 int elementwise_blocks(int64_t n);
+int backproject_blocks(const GeomDev &g);
+int transpose_blocks(int nx, int ny, int nz);
+
+// ------------------------------------------------------------ batched solve
+// One problem of a batch, resident in device memory.  Every phase of a UPN /
+// GP round is one grouped launch over all problems; a block finds its
+// problem in a prefix table of block counts and reads its operands here.
+// The control kernel (one thread per problem) takes the line-search and
+// momentum decisions in double and swaps the pointers for the next round,
+// so a captured graph of the round can be replayed unchanged.
+enum BatchState : int { B_RUNNING = 0, B_CONVERGED = 1, B_NOTCONV = 2, B_STALL = 3 };
+
+template <typename T>
+struct BatchProblem {
+    GeomDev g;
+    int N, m;
+    int nb_vox, nb_proj, nb_ew, pstride;
+    T *X, *XB, *YB, *G, *XT, *RX, *RXB, *RYB;
+    T *Y, *RY;        // current auxiliary point and its residual (alias X/RX or YB/RYB)
+    const T *b;
+    double *part;     // per-block partial sums [S_COUNT][pstride]
+    double *sum;      // finalised sums [S_COUNT]
+    double alpha, tau, eps, rho, mu_bar;
+    double L, mu, theta, beta, gm0, gm, phi;
+    int method, stop_mode, max_iter, max_trials;
+    int state, first, need_grad, ex, distinct, have_ry2, ry2_pending, trials;
+    int iters, grad_evals, func_evals;
+};
+
+// Grouped launches; offs[p] = first block of problem p (n + 1 entries).
+template <typename T>
+hipError_t launch_backproject_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                                      hipStream_t st);
+template <typename T>
+hipError_t launch_tv_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_trial_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_transpose_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                                    hipStream_t st);
+template <typename T>
+hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                                  hipStream_t st);
+template <typename T>
+hipError_t launch_extrapolate_grouped(BatchProblem<T> *probs, const int *offs, int n,
+                                      int blocks, hipStream_t st);
+template <typename T>
+hipError_t launch_finalize_grouped(BatchProblem<T> *probs, int n, hipStream_t st);
+template <typename T>
+hipError_t launch_control_batched(BatchProblem<T> *probs, int n, int *running, hipStream_t st);
 
 }  // namespace tvr

@@ -78,8 +78,13 @@ def test_null_arguments_rejected(tv):
     assert L.tvreg_tv_grad(0, 4, 4, tv.F32, 1e-4, None, None, None, None, 0, None) == tv.EINVAL
     assert L.tvreg_tv_grad(4, 4, 4, tv.F32, -1.0, ctypes.c_void_p(16), ctypes.c_void_p(16),
                            None, None, 0, None) == tv.EINVAL
-    assert L.tvreg_tv_workspace_bytes(64, 64, 64) >= 8 * 64 ** 3 // 256
+    assert 8 <= L.tvreg_tv_workspace_bytes(64, 64, 64) <= L.tvreg_tv_workspace_bytes(128, 128, 128)
     assert L.tvreg_solve_workspace_bytes(None, tv.UPN) == 0
+    assert L.tvreg_solve_batched_workspace_bytes(0, None) == 0
+    assert L.tvreg_solve_batched(0, None, None, None, None, None, 0, 8, None, None) == tv.EINVAL
+    one = (ctypes.c_void_p * 1)(None)
+    assert L.tvreg_solve_batched_workspace_bytes(1, one) == 0
+    assert L.tvreg_solve_batched(1, one, one, None, one, None, 0, 8, None, None) == tv.EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):
