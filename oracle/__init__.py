@@ -23,6 +23,11 @@ solve (GP)        eq. 6 + Alg. 2 (BT)                     alpha = 0 vs scipy.opt
 solve (GPBB)      Alg. 1                                  all three methods reach the same minimiser;
 solve (UPN)       Alg. 3 + eq. 9                          invariants (L monotone, mu in [0, mu_bar]);
                                                           mu := L reduces UPN to GP bit for bit
+tv_hessvec        derivative of the TV gradient (eq. 2)   central differences of tv's gradient;
+                                                          symmetry; quadratic regime = Laplacian
+unrolled          K steps of Alg. 3 and the reverse-mode   K = 1 closed form; central differences
+                  gradient of l(x^(K)) in alpha and b      of the replayed forward map (same
+                  (not a passage of the paper)            masks and regimes on both sides)
 ================  =====================================  =========================================
 """
 from __future__ import annotations
@@ -120,6 +125,13 @@ def lib():
         L.og_huber_bregman.restype = ctypes.c_double
         L.og_tv_bregman.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, dp, dp]
         L.og_tv_bregman.restype = ctypes.c_double
+        L.og_tv_hessvec.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, dp, dp, dp]
+        L.og_tv_hessvec.restype = None
+        L.og_unrolled.argtypes = [gp, dp, ctypes.POINTER(_Params), ctypes.c_int32,
+                                  ctypes.c_int32, dp, dp, dp, dp, dp, dp, dp,
+                                  ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+        L.og_unrolled.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -298,6 +310,53 @@ def noisy_data(g, x_true, unit_noise, eta: float) -> np.ndarray:
     sigma = eta * float(np.linalg.norm(ax)) / np.sqrt(ax.size)
     b = ax + sigma * np.asarray(unit_noise, np.float64).reshape(ax.shape)
     return b.astype(np.float32).astype(np.float64)
+
+
+def tv_hessvec(y, v, tau: float) -> np.ndarray:
+    """H(y) v, the Hessian of the smoothed TV at y applied to v."""
+    y = _f64(y)
+    nz, ny, nx = y.shape
+    out = np.zeros_like(y)
+    lib().og_tv_hessvec(nx, ny, nz, tau, _dp(y), _dp(_f64(v).reshape(y.shape)), _dp(out))
+    return out
+
+
+def unrolled(g, b, K: int, alpha: float, tau: float = 1e-4, L=None, xK_bar=None,
+             L_bar: float = 1.0, rho_L: float = 2.0, mu_bar: float = 0.0,
+             max_trials: int = 60, bt_form: int = 1) -> dict:
+    """K unrolled UPN steps from x = 0 (og_unrolled).
+
+    L=None runs BT for every step; an array of K values replays them.  With
+    xK_bar = dl/dx^(K) the reverse pass returns dl/dalpha and dl/db.
+    Returns a dict with xK, L, mu, beta, mu_state, signature, status and,
+    with xK_bar, alpha_bar and b_bar."""
+    G = _geom(g)
+    p = _Params(**default_params(UPN, alpha, tau, L_bar=L_bar, rho_L=rho_L, mu_bar=mu_bar,
+                                 max_trials=max_trials, bt_form=bt_form))
+    replay = L is not None
+    Ls = _f64(L).copy() if replay else np.zeros(K)
+    assert Ls.shape == (K,)
+    xK = np.zeros(G.vol_shape)
+    mu = np.zeros(K)
+    beta = np.zeros(K)
+    state = np.zeros(K, np.int32)
+    sig = ctypes.c_uint64(0)
+    abar = np.zeros(1)
+    bbar = np.zeros(G.proj_shape)
+    xb = _f64(xK_bar).reshape(G.vol_shape) if xK_bar is not None else None
+    st = lib().og_unrolled(G.ref, _dp(_f64(b).reshape(G.proj_shape)), ctypes.byref(p), K,
+                           1 if replay else 0, _dp(Ls), _dp(xK),
+                           _dp(xb) if xb is not None else None,
+                           _dp(abar) if xb is not None else None,
+                           _dp(bbar) if xb is not None else None, _dp(mu), _dp(beta),
+                           state.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           ctypes.byref(sig))
+    out = dict(status=int(st), xK=xK, L=Ls, mu=mu, beta=beta, mu_state=state,
+               signature=int(sig.value))
+    if xb is not None:
+        out["alpha_bar"] = float(abar[0])
+        out["b_bar"] = bbar
+    return out
 
 
 def num_threads() -> int:

@@ -955,3 +955,321 @@ int32_t og_solve_dense(int32_t m, int32_t nx, int32_t ny, int32_t nz, const doub
     og_op op = {m, (int64_t)nx * ny * nz, nx, ny, nz, NULL, A};
     return solve_op(&op, b, p, x, info, hist_phi, hist_gm, hist_L, hist_mu, hist_len);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Differentiated form: K unrolled UPN steps and their reverse-mode adjoint  */
+/* (not a passage of the paper; it differentiates the map Alg. 3 applies)    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Hessian of the smoothed TV applied to v:
+ *   H(y) v = sum_j D_j^T dq_j,   dq_j = d/dt [D_j(y + t v) / max(tau, |D_j(y + t v)|)]
+ * which is D_j v / tau where |D_j y| < tau, and (e - u (u.e)) / |D_j y| with
+ * u = D_j y / |D_j y|, e = D_j v where |D_j y| >= tau (the regime split of
+ * og_tv; the Hessian jumps across |D_j y| = tau).
+ */
+void og_tv_hessvec(int32_t nx, int32_t ny, int32_t nz, double tau, const double *y,
+                   const double *v, double *out)
+{
+    int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+    int64_t N = sz * nz;
+    memset(out, 0, sizeof(double) * (size_t)N);
+    for (int32_t k = 0; k < nz; ++k)
+        for (int32_t j = 0; j < ny; ++j)
+            for (int32_t i = 0; i < nx; ++i) {
+                int64_t q = i * sx + j * sy + k * sz;
+                int in[3] = {i + 1 < nx, j + 1 < ny, k + 1 < nz};
+                int64_t st[3] = {sx, sy, sz};
+                double a[3], e[3], dq[3];
+                for (int c = 0; c < 3; ++c) {
+                    a[c] = in[c] ? y[q + st[c]] - y[q] : 0.0;
+                    e[c] = in[c] ? v[q + st[c]] - v[q] : 0.0;
+                }
+                double n = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+                if (n >= tau) {
+                    double ue = (a[0] * e[0] + a[1] * e[1] + a[2] * e[2]) / n;
+                    for (int c = 0; c < 3; ++c)
+                        dq[c] = (e[c] - (a[c] / n) * ue) / n;
+                } else {
+                    for (int c = 0; c < 3; ++c)
+                        dq[c] = e[c] / tau;
+                }
+                out[q] -= dq[0] + dq[1] + dq[2];
+                for (int c = 0; c < 3; ++c)
+                    if (in[c])
+                        out[q + st[c]] += dq[c];
+            }
+}
+
+/* FNV-style fold of the discrete pattern a step's derivative depends on */
+static uint64_t fold(uint64_t h, uint64_t v)
+{
+    h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+    return h;
+}
+
+static uint64_t pattern_signature(uint64_t h, int32_t nx, int32_t ny, int32_t nz, double tau,
+                                  const double *y, const double *xn)
+{
+    int64_t sy = nx, sz = (int64_t)nx * ny, N = sz * nz;
+    for (int64_t q = 0; q < N; ++q)
+        if (xn[q] > 0.0)
+            h = fold(h, (uint64_t)q);
+    for (int32_t k = 0; k < nz; ++k)
+        for (int32_t j = 0; j < ny; ++j)
+            for (int32_t i = 0; i < nx; ++i) {
+                int64_t q = i + j * sy + k * sz;
+                double dx = (i + 1 < nx) ? y[q + 1] - y[q] : 0.0;
+                double dy = (j + 1 < ny) ? y[q + sy] - y[q] : 0.0;
+                double dz = (k + 1 < nz) ? y[q + sz] - y[q] : 0.0;
+                if (sqrt(dx * dx + dy * dy + dz * dz) >= tau)
+                    h = fold(h, (uint64_t)(N + q));
+            }
+    return h;
+}
+
+/*
+ * K steps of UPN (Alg. 3) from x^(0) = 0, output x^(K) (the K-th BT output),
+ * and, when xK_bar != NULL, the gradient of l(x^(K)) with respect to alpha
+ * and b given xK_bar = dl/dx^(K).
+ *
+ * Forward.  Step j maps y^(j) to x^(j+1) = P_Q(y^(j) - grad f(y^(j)) / L_j).
+ * L_j comes from BT (Alg. 2, started at L_bar for j = 0 and at L_{j-1}
+ * after) or, with replay != 0, is read from L[j] with no test.  After step 0:
+ * mu_0 = mu_bar (or L_0 / 4 when mu_bar <= 0), theta_1 = sqrt(mu_0 / L_0),
+ * y^(1) = x^(1).  After step j >= 1: mu_j = max(min(mu_{j-1}, M_j), 0) with
+ * M_j = Bregman_f(x^(j), y^(j)) / (|x^(j) - y^(j)|^2 / 2) (eq. 9, evaluated
+ * only when x^(j) != y^(j)); theta_{j+1} is the positive root of
+ * t^2 = (1 - t) theta_j^2 + (mu_j / L_j) t; beta_j = theta_j (1 - theta_j) /
+ * (theta_j^2 + theta_{j+1}); y^(j+1) = x^(j+1) + beta_j (x^(j+1) - x^(j)).
+ *
+ * Reverse.  The L_j are held fixed (they are decisions, not functions of
+ * the inputs); the min in mu_j is differentiated on the branch it took; the
+ * projection P_Q contributes the mask [x^(j+1) > 0].  With z = y - grad f(y)/L
+ * and grad f(y) = A^T (A y - b) + alpha grad T(y):
+ *   dz/dy = I - (A^T A + alpha H(y)) / L,  dz/db = A^T / L,
+ *   dz/dalpha = -grad T(y) / L.
+ * theta_{j+1} solves F = t^2 + (theta_j^2 - q) t - theta_j^2 = 0, q = mu_j/L_j,
+ * so dt/dtheta_j = 2 theta_j (1 - t) / s and dt/dq = t / s with
+ * s = dF/dt = 2 t + theta_j^2 - q.  With d = x - y, D = |d|^2 / 2 and
+ * M = (|A d|^2 / 2 + alpha B_T(x, y)) / D:
+ *   dM/dx = (A^T A d + alpha (grad T(x) - grad T(y)) - M d) / D,
+ *   dM/dy = (-A^T A d - alpha H(y) d + M d) / D,   dM/dalpha = B_T / D.
+ * Every iterate is kept in memory (no checkpointing).
+ *
+ * mu_state[j]: 3 for step 0, 0 carried (mu_j = mu_{j-1}), 1 M_j taken,
+ * 2 clamped to 0.  *signature folds the projection masks and the Huber
+ * regimes met by the forward pass (equal signatures: same smooth piece).
+ * Returns 0, or OG_STALL when a BT search hits max_trials (no reverse pass).
+ */
+int32_t og_unrolled(const og_geom *g, const double *b, const og_params *p, int32_t K,
+                    int32_t replay, double *L, double *xK, const double *xK_bar,
+                    double *alpha_bar, double *b_bar, double *mu_out, double *beta_out,
+                    int32_t *mu_state, uint64_t *signature)
+{
+    og_op op = {n_rays(g), (int64_t)g->nx * g->ny * g->nz, g->nx, g->ny, g->nz, g, NULL};
+    const int64_t N = op.N, m = op.m;
+    const double alpha = p->alpha, tau = p->tau;
+    double *xs = (double *)calloc((size_t)(K + 1) * N, sizeof(double)); /* x^(0..K) */
+    double *ys = (double *)calloc((size_t)K * N, sizeof(double));       /* y^(0..K-1) */
+    double *gy = (double *)malloc(sizeof(double) * N);
+    double *tm = (double *)malloc(sizeof(double) * m);
+    double *tn = (double *)malloc(sizeof(double) * N);
+    double *theta = (double *)calloc((size_t)K + 2, sizeof(double));
+    double *mu = (double *)calloc((size_t)K, sizeof(double));
+    double *beta = (double *)calloc((size_t)K, sizeof(double));
+    double *Mv = (double *)calloc((size_t)K, sizeof(double));
+    double *Bv = (double *)calloc((size_t)K, sizeof(double));
+    double *Dv = (double *)calloc((size_t)K, sizeof(double));
+    int32_t *state = (int32_t *)calloc((size_t)K, sizeof(int32_t));
+    og_info info;
+    memset(&info, 0, sizeof(info));
+    int32_t status = 0;
+    uint64_t sig = 1469598103934665603ULL;
+
+    /* ---- forward ---- */
+    for (int32_t j = 0; j < K; ++j) {
+        double *y = ys + (size_t)j * N, *xn = xs + (size_t)(j + 1) * N;
+        double *xj = xs + (size_t)j * N;
+        double fy = op_fg(&op, b, alpha, tau, y, gy, tm, tn);
+        double Lj;
+        if (replay) {
+            Lj = L[j];
+            for (int64_t q = 0; q < N; ++q)
+                xn[q] = pq(y[q] - gy[q] / Lj);
+        } else {
+            double fx;
+            double L0 = j == 0 ? p->L_bar : L[j - 1];
+            if (op_bt(&op, b, p, y, fy, gy, L0, xn, &fx, &Lj, tm, tn, &info) != 0) {
+                status = OG_STALL;
+                goto out;
+            }
+            L[j] = Lj;
+        }
+        sig = pattern_signature(sig, g->nx, g->ny, g->nz, tau, y, xn);
+        if (j == 0) {
+            mu[0] = p->mu_bar > 0.0 ? p->mu_bar : 0.25 * Lj;
+            state[0] = 3;
+            theta[1] = sqrt(mu[0] / Lj);
+            beta[0] = 0.0;
+            if (K > 1)
+                memcpy(ys + (size_t)N, xn, sizeof(double) * N);
+            continue;
+        }
+        double nd = dist2(N, xj, y);
+        double mu_j = mu[j - 1];
+        state[j] = 0;
+        if (nd > 0.0) {
+            /* Bregman_f(x, y) = |A (x - y)|^2 / 2 + alpha B_T(x, y) */
+            for (int64_t q = 0; q < N; ++q)
+                tn[q] = xj[q] - y[q];
+            op_apply(&op, tn, tm);
+            double a2 = 0.0;
+            for (int64_t i = 0; i < m; ++i)
+                a2 += tm[i] * tm[i];
+            Bv[j] = alpha != 0.0 ? og_tv_bregman(g->nx, g->ny, g->nz, tau, xj, y) : 0.0;
+            Dv[j] = 0.5 * nd;
+            Mv[j] = (0.5 * a2 + alpha * Bv[j]) / Dv[j];
+            if (Mv[j] < mu_j) {
+                if (Mv[j] >= 0.0) {
+                    mu_j = Mv[j];
+                    state[j] = 1;
+                } else {
+                    mu_j = 0.0;
+                    state[j] = 2;
+                }
+            }
+        }
+        mu[j] = mu_j;
+        double q = mu_j / Lj, th = theta[j], th2 = th * th, bq = th2 - q;
+        theta[j + 1] = 0.5 * (-bq + sqrt(bq * bq + 4.0 * th2));
+        beta[j] = th * (1.0 - th) / (th2 + theta[j + 1]);
+        if (j + 1 < K) {
+            double *yn = ys + (size_t)(j + 1) * N;
+            for (int64_t r = 0; r < N; ++r)
+                yn[r] = xn[r] + beta[j] * (xn[r] - xj[r]);
+        }
+    }
+    memcpy(xK, xs + (size_t)K * N, sizeof(double) * N);
+
+    /* ---- reverse ---- */
+    if (xK_bar) {
+        double *xb_next = (double *)malloc(sizeof(double) * N); /* adjoint of x^(j+1) */
+        double *xb_cur = (double *)calloc((size_t)N, sizeof(double));
+        double *yb_next = (double *)calloc((size_t)N, sizeof(double));
+        double *yb_cur = (double *)calloc((size_t)N, sizeof(double));
+        double *zb = (double *)malloc(sizeof(double) * N);
+        double *w = (double *)malloc(sizeof(double) * N);
+        double *h = (double *)malloc(sizeof(double) * N);
+        double *gT = (double *)malloc(sizeof(double) * N);
+        double *gT2 = (double *)malloc(sizeof(double) * N);
+        double *pm = (double *)malloc(sizeof(double) * m);
+        double *theta_bar = (double *)calloc((size_t)K + 2, sizeof(double));
+        double *mu_bar = (double *)calloc((size_t)K, sizeof(double));
+        double abar = 0.0;
+        memcpy(xb_next, xK_bar, sizeof(double) * N);
+        memset(b_bar, 0, sizeof(double) * m);
+        for (int32_t j = K - 1; j >= 0; --j) {
+            const double *xj = xs + (size_t)j * N, *xn = xs + (size_t)(j + 1) * N;
+            const double *y = ys + (size_t)j * N;
+            const double Lj = L[j];
+            /* extrapolation and scalar schedule of step j (y^(j+1) is used by step j+1) */
+            if (j >= 1 && j + 1 < K) {
+                double bb = 0.0;
+                for (int64_t r = 0; r < N; ++r)
+                    bb += yb_next[r] * (xn[r] - xj[r]);
+                for (int64_t r = 0; r < N; ++r) {
+                    xb_next[r] += (1.0 + beta[j]) * yb_next[r];
+                    xb_cur[r] += -beta[j] * yb_next[r];
+                }
+                double th = theta[j], tn1 = theta[j + 1];
+                double num = th * (1.0 - th), den = th * th + tn1;
+                theta_bar[j] += bb * ((1.0 - 2.0 * th) / den - num * 2.0 * th / (den * den));
+                theta_bar[j + 1] += bb * (-num / (den * den));
+                double q = mu[j] / Lj;
+                double s = 2.0 * tn1 + th * th - q;
+                theta_bar[j] += theta_bar[j + 1] * 2.0 * th * (1.0 - tn1) / s;
+                mu_bar[j] += theta_bar[j + 1] * (tn1 / s) / Lj;
+                if (state[j] == 0) {
+                    mu_bar[j - 1] += mu_bar[j];
+                } else if (state[j] == 1) {
+                    double c = mu_bar[j] / Dv[j], M = Mv[j];
+                    for (int64_t r = 0; r < N; ++r)
+                        tn[r] = xj[r] - y[r];                   /* d */
+                    op_apply(&op, tn, tm);
+                    op_apply_t(&op, tm, w);                    /* A^T A d */
+                    og_tv(g->nx, g->ny, g->nz, tau, xj, gT);   /* grad T(x) */
+                    og_tv(g->nx, g->ny, g->nz, tau, y, gT2);   /* grad T(y) */
+                    og_tv_hessvec(g->nx, g->ny, g->nz, tau, y, tn, h); /* H(y) d */
+                    for (int64_t r = 0; r < N; ++r) {
+                        xb_cur[r] += c * (w[r] + alpha * (gT[r] - gT2[r]) - M * tn[r]);
+                        yb_cur[r] += c * (-w[r] - alpha * h[r] + M * tn[r]);
+                    }
+                    abar += mu_bar[j] * Bv[j] / Dv[j];
+                }
+            } else if (j == 0 && K > 1) {
+                for (int64_t r = 0; r < N; ++r)
+                    xb_next[r] += yb_next[r]; /* y^(1) = x^(1) */
+            }
+            /* step j: x^(j+1) = P_Q(y^(j) - grad f(y^(j)) / L_j) */
+            for (int64_t r = 0; r < N; ++r)
+                zb[r] = xn[r] > 0.0 ? xb_next[r] : 0.0;
+            op_apply(&op, zb, pm);
+            for (int64_t i = 0; i < m; ++i)
+                b_bar[i] += pm[i] / Lj;
+            op_apply_t(&op, pm, w);
+            og_tv(g->nx, g->ny, g->nz, tau, y, gT);
+            og_tv_hessvec(g->nx, g->ny, g->nz, tau, y, zb, h);
+            double zg = 0.0;
+            for (int64_t r = 0; r < N; ++r) {
+                yb_cur[r] += zb[r] - (w[r] + alpha * h[r]) / Lj;
+                zg += zb[r] * gT[r];
+            }
+            abar += -zg / Lj;
+            /* shift: x^(j) and y^(j) become the next step's outputs */
+            double *t = xb_next;
+            xb_next = xb_cur;
+            xb_cur = t;
+            memset(xb_cur, 0, sizeof(double) * N);
+            t = yb_next;
+            yb_next = yb_cur;
+            yb_cur = t;
+            memset(yb_cur, 0, sizeof(double) * N);
+        }
+        *alpha_bar = abar;
+        free(xb_next);
+        free(xb_cur);
+        free(yb_next);
+        free(yb_cur);
+        free(zb);
+        free(w);
+        free(h);
+        free(gT);
+        free(gT2);
+        free(pm);
+        free(theta_bar);
+        free(mu_bar);
+    }
+out:
+    if (mu_out)
+        memcpy(mu_out, mu, sizeof(double) * K);
+    if (beta_out)
+        memcpy(beta_out, beta, sizeof(double) * K);
+    if (mu_state)
+        memcpy(mu_state, state, sizeof(int32_t) * K);
+    if (signature)
+        *signature = sig;
+    free(xs);
+    free(ys);
+    free(gy);
+    free(tm);
+    free(tn);
+    free(theta);
+    free(mu);
+    free(beta);
+    free(Mv);
+    free(Bv);
+    free(Dv);
+    free(state);
+    return status;
+}

@@ -94,6 +94,16 @@ int32_t og_solve_dense(int32_t m, int32_t nx, int32_t ny, int32_t nz, const doub
                        double *hist_phi, double *hist_gm, double *hist_L, double *hist_mu,
                        int32_t hist_len);
 
+/* differentiated form: Hessian-vector product of the smoothed TV, and K
+   unrolled UPN steps from x = 0 with the reverse-mode gradient of
+   l(x^(K)) with respect to alpha and b (L decisions held fixed) */
+void og_tv_hessvec(int32_t nx, int32_t ny, int32_t nz, double tau, const double *y,
+                   const double *v, double *out);
+int32_t og_unrolled(const og_geom *g, const double *b, const og_params *p, int32_t K,
+                    int32_t replay, double *L, double *xK, const double *xK_bar,
+                    double *alpha_bar, double *b_bar, double *mu_out, double *beta_out,
+                    int32_t *mu_state, uint64_t *signature);
+
 int32_t og_num_threads(void);
 
 #ifdef __cplusplus
