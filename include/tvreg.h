@@ -111,6 +111,20 @@ tvreg_status tvreg_tv_grad(int32_t nx, int32_t ny, int32_t nz, tvreg_precision p
                            double tau, const void *x_dev, void *grad_dev, double *tv_value_dev,
                            void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/*
+ * out_dev = H(y) v, the Hessian of T_tau at y applied to v (the derivative of
+ * the gradient above along v): sum_j D_j^T dq_j with dq_j = D_j v / tau where
+ * |D_j y| < tau and (e - u (u.e)) / |D_j y|, u = D_j y / |D_j y|, e = D_j v,
+ * where |D_j y| >= tau.  With grad_dot_dev != NULL also *grad_dot_dev =
+ * <v, grad T_tau(y)> (double, device; needs the workspace of
+ * tvreg_tv_workspace_bytes).  out must not alias y or v.  Used by the
+ * reverse pass of the unrolled solver; exposed for testing and reuse.
+ */
+tvreg_status tvreg_tv_hessvec(int32_t nx, int32_t ny, int32_t nz, tvreg_precision precision,
+                              double tau, const void *y_dev, const void *v_dev, void *out_dev,
+                              double *grad_dot_dev, void *workspace_dev, size_t workspace_bytes,
+                              void *stream);
+
 /* Bytes of device workspace tvreg_objective_grad needs for this geometry. */
 size_t tvreg_objective_workspace_bytes(const tvreg_geometry *geom);
 
@@ -202,6 +216,38 @@ tvreg_status tvreg_solve_batched(int32_t n, const tvreg_geometry *const *geoms,
                                  void *const *x_inout_dev, void *workspace_dev,
                                  size_t workspace_bytes, int32_t poll_rounds,
                                  tvreg_solve_info *infos, void *stream);
+
+/*
+ * Differentiated form of UPN (not a passage of the paper: it differentiates
+ * the map Alg. 3 applies).  The forward pass runs K UPN steps from x = 0:
+ * step j maps y^(j) to x^(j+1) = P_Q(y^(j) - grad f(y^(j)) / L_j) with L_j
+ * from BT (Alg. 2 in Bregman form, started at L_bar, then at L_{j-1}) or,
+ * when L_replay != NULL, taken from L_replay[j] with no test; mu_j follows
+ * eq. 9 (skipped while x^(j) = y^(j)), theta and beta follow Alg. 3, and
+ * xK_dev receives x^(K) (the K-th BT output).  Uses params->alpha, tau,
+ * L_bar, mu_bar, rho_L and max_trials.  The tape (device workspace of
+ * tvreg_unrolled_workspace_bytes) keeps the step scalars and (x, y) every
+ * ckpt_every steps; L_out (host, K entries, may be NULL) receives the L_j.
+ * Returns TVREG_ESTALL when a BT search hits max_trials (no gradient then).
+ *
+ * The reverse pass, given dl/dx^(K) (N values of T, device), writes
+ * *dl_dlogalpha (host double) and dl_db_dev (m values of T): the gradient of
+ * l(x^(K)) with the L_j held fixed (decisions, not functions of alpha or b),
+ * the min of eq. 9 differentiated on the branch the forward pass took and
+ * P_Q through its mask [x^(j+1) > 0].  It recomputes each segment of
+ * ckpt_every steps from its checkpoint (bit-identical to the forward pass)
+ * and reads alpha, tau, K and ckpt_every from the tape.  b_dev must be the
+ * data of the forward pass.  Both calls synchronise `stream`.
+ */
+size_t tvreg_unrolled_workspace_bytes(const tvreg_geometry *geom, int32_t K, int32_t ckpt_every);
+tvreg_status tvreg_upn_unrolled_fwd(const tvreg_geometry *geom, const void *b_dev,
+                                    const tvreg_solve_params *params, int32_t K,
+                                    int32_t ckpt_every, const double *L_replay, double *L_out,
+                                    void *xK_dev, void *tape_dev, size_t tape_bytes,
+                                    void *stream);
+tvreg_status tvreg_upn_unrolled_bwd(const tvreg_geometry *geom, const void *b_dev,
+                                    void *tape_dev, size_t tape_bytes, const void *xK_bar_dev,
+                                    double *dl_dlogalpha, void *dl_db_dev, void *stream);
 
 /*
  * Opt-in instrumentation of tvreg_solve: when enabled, every kernel launch of

@@ -57,10 +57,11 @@ class _SolveInfo(ctypes.Structure):
 
 # Every symbol include/tvreg.h declares.
 EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
-           "tvreg_backproject", "tvreg_tv_workspace_bytes", "tvreg_tv_grad",
+           "tvreg_backproject", "tvreg_tv_workspace_bytes", "tvreg_tv_grad", "tvreg_tv_hessvec",
            "tvreg_objective_workspace_bytes", "tvreg_objective_grad",
            "tvreg_solve_workspace_bytes", "tvreg_solve", "tvreg_solve_batched_workspace_bytes",
-           "tvreg_solve_batched", "tvreg_profile_enable", "tvreg_profile_reset",
+           "tvreg_solve_batched", "tvreg_unrolled_workspace_bytes", "tvreg_upn_unrolled_fwd",
+           "tvreg_upn_unrolled_bwd", "tvreg_profile_enable", "tvreg_profile_reset",
            "tvreg_profile_get", "tvreg_last_error", "tvreg_version")
 
 KERNELS = {"project": 0, "backproject": 1, "tv": 2, "trial": 3, "extrapolate": 4,
@@ -70,7 +71,7 @@ KERNELS = {"project": 0, "backproject": 1, "tv": 2, "trial": 3, "extrapolate": 4
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          f"`python -m paper_1105_4002_amd.build` (no CPU fallback exists)")
+                          f"`python paper_1105_4002_amd/build.py` (no CPU fallback exists)")
     L = ctypes.CDLL(LIB_PATH)
     vp, sz, st = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
     L.tvreg_create_geometry.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int,
@@ -87,6 +88,9 @@ def _load():
     L.tvreg_tv_grad.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int, ctypes.c_double, vp, vp,
                                                        vp, vp, sz, vp]
     L.tvreg_tv_grad.restype = st
+    L.tvreg_tv_hessvec.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int, ctypes.c_double, vp, vp,
+                                                          vp, vp, vp, sz, vp]
+    L.tvreg_tv_hessvec.restype = st
     L.tvreg_objective_workspace_bytes.argtypes = [vp]
     L.tvreg_objective_workspace_bytes.restype = sz
     L.tvreg_objective_grad.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp,
@@ -103,6 +107,14 @@ def _load():
                                       ctypes.POINTER(_SolveParams), ctypes.POINTER(vp), vp, sz,
                                       ctypes.c_int32, ctypes.POINTER(_SolveInfo), vp]
     L.tvreg_solve_batched.restype = st
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.tvreg_unrolled_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.tvreg_unrolled_workspace_bytes.restype = sz
+    L.tvreg_upn_unrolled_fwd.argtypes = [vp, vp, ctypes.POINTER(_SolveParams), ctypes.c_int32,
+                                         ctypes.c_int32, dp, dp, vp, vp, sz, vp]
+    L.tvreg_upn_unrolled_fwd.restype = st
+    L.tvreg_upn_unrolled_bwd.argtypes = [vp, vp, vp, sz, vp, dp, vp, vp]
+    L.tvreg_upn_unrolled_bwd.restype = st
     L.tvreg_profile_enable.argtypes = [ctypes.c_int32]
     L.tvreg_profile_enable.restype = None
     L.tvreg_profile_reset.argtypes = []
@@ -220,6 +232,23 @@ def tv_grad(x: torch.Tensor, tau: float, value: bool = True, grad: bool = True):
                               ctypes.c_void_p(ws.data_ptr()) if value else None, wsb,
                               _stream(x)), "tvreg_tv_grad")
     return g, val
+
+
+def tv_hessvec(y: torch.Tensor, v: torch.Tensor, tau: float, dot: bool = True):
+    """(H_T(y) v, <v, grad T(y)>) (tvreg_tv_hessvec); the dot is a 0-d float64 tensor."""
+    nz, ny, nx = y.shape
+    prec = F64 if y.dtype == torch.float64 else F32
+    n = nx * ny * nz
+    out = torch.empty_like(y)
+    val = torch.empty((), dtype=torch.float64, device=y.device) if dot else None
+    wsb = _lib.tvreg_tv_workspace_bytes(nx, ny, nz) if dot else 0
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=y.device) if dot else None
+    _check(_lib.tvreg_tv_hessvec(nx, ny, nz, prec, float(tau), _ptr(y, y.dtype, n, "y"),
+                                 _ptr(v, y.dtype, n, "v"), _ptr(out, y.dtype, n, "out"),
+                                 ctypes.c_void_p(val.data_ptr()) if dot else None,
+                                 ctypes.c_void_p(ws.data_ptr()) if dot else None, wsb,
+                                 _stream(y)), "tvreg_tv_hessvec")
+    return out, val
 
 
 def objective_grad(geom: Geometry, b: torch.Tensor, alpha: float, tau: float, x: torch.Tensor,
@@ -356,3 +385,55 @@ def profile_stats() -> dict:
 
 def version() -> str:
     return _lib.tvreg_version().decode()
+
+
+def unrolled_workspace(geom: Geometry, K: int, ckpt_every: int = 5, device="cuda"):
+    nb = _lib.tvreg_unrolled_workspace_bytes(geom.handle, int(K), int(ckpt_every))
+    if nb == 0:
+        raise ValueError("need K >= 1 and ckpt_every >= 1")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def upn_unrolled_fwd(geom: Geometry, b: torch.Tensor, K: int, alpha: float, tau: float = 1e-4,
+                     ckpt_every: int = 5, L_replay=None, L_bar: float = 1.0,
+                     mu_bar: float = 0.0, rho_L: float = 2.0, max_trials: int = 60,
+                     tape: Optional[torch.Tensor] = None):
+    """K unrolled UPN steps from x = 0 (tvreg_upn_unrolled_fwd).
+
+    Returns (x^(K), tape, list of the K values of L used).  L_replay (K
+    values) replaces the BT searches.  Raises TvregError also for
+    TVREG_ESTALL (a BT search hit max_trials)."""
+    tape = tape if tape is not None else unrolled_workspace(geom, K, ckpt_every, b.device)
+    p = _SolveParams(UPN, float(alpha), float(tau), 0.0, 0, 1, float(L_bar), float(mu_bar),
+                     float(rho_L), 2, 0.1, 0.95, int(max_trials), None, None, None, 0)
+    Lout = (ctypes.c_double * K)()
+    Lin = None
+    if L_replay is not None:
+        if len(L_replay) != K:
+            raise ValueError("L_replay needs K values")
+        Lin = (ctypes.c_double * K)(*[float(v) for v in L_replay])
+    xK = geom.empty_volume(b.device)
+    st = _lib.tvreg_upn_unrolled_fwd(geom.handle, _ptr(b, geom.dtype, geom.m, "b"),
+                                     ctypes.byref(p), int(K), int(ckpt_every),
+                                     ctypes.cast(Lin, _c_dp) if Lin is not None else None,
+                                     ctypes.cast(Lout, _c_dp),
+                                     _ptr(xK, geom.dtype, geom.N, "xK"),
+                                     ctypes.c_void_p(tape.data_ptr()), tape.numel(), _stream(b))
+    if st != OK:  # a stalled line search leaves no x^(K) either
+        raise TvregError(st, "tvreg_upn_unrolled_fwd")
+    return xK, tape, list(Lout)
+
+
+def upn_unrolled_bwd(geom: Geometry, b: torch.Tensor, tape: torch.Tensor, xK_bar: torch.Tensor):
+    """Reverse pass (tvreg_upn_unrolled_bwd): (dl/dlog alpha as float, dl/db)."""
+    db = geom.empty_data(b.device)
+    da = ctypes.c_double(0.0)
+    _check(_lib.tvreg_upn_unrolled_bwd(geom.handle, _ptr(b, geom.dtype, geom.m, "b"),
+                                       ctypes.c_void_p(tape.data_ptr()), tape.numel(),
+                                       _ptr(xK_bar.contiguous(), geom.dtype, geom.N, "xK_bar"),
+                                       ctypes.byref(da), _ptr(db, geom.dtype, geom.m, "dl_db"),
+                                       _stream(b)), "tvreg_upn_unrolled_bwd")
+    return float(da.value), db
+
+
+from .unrolled import UnrolledUPN, unrolled_upn  # noqa: E402  (uses the functions above)

@@ -1,6 +1,7 @@
 """Builds libtvreg.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1105_4002_amd.build   (or call build()).
+Usage: python paper_1105_4002_amd/build.py   (run as a file: importing the
+package first would load the library this script builds).
 """
 from __future__ import annotations
 
@@ -16,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build", "tvreg")
 LIB_PATH = os.path.join(PKG, "libtvreg.so")
-SOURCES = ["project.hip", "backproject.hip", "stencil.hip", "batch.hip", "api.hip"]
+SOURCES = ["project.hip", "backproject.hip", "stencil.hip", "adjoint.hip", "batch.hip",
+           "unrolled.hip", "api.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

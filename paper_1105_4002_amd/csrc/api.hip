@@ -306,6 +306,49 @@ extern "C" tvreg_status tvreg_tv_grad(int32_t nx, int32_t ny, int32_t nz,
     return TVREG_OK;
 }
 
+extern "C" tvreg_status tvreg_tv_hessvec(int32_t nx, int32_t ny, int32_t nz,
+                                         tvreg_precision precision, double tau, const void *y,
+                                         const void *v, void *out, double *grad_dot, void *ws,
+                                         size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    if (nx < 1 || ny < 1 || nz < 1)
+        return fail(TVREG_EINVAL, "sizes must be >= 1");
+    if ((int64_t)nx * ny * nz >= (int64_t(1) << 31))
+        return fail(TVREG_EINVAL, "volume larger than 2^31 entries");
+    if (!y || !v || !out)
+        return fail(TVREG_EINVAL, "NULL y, v or out");
+    if (out == y || out == v)
+        return fail(TVREG_EINVAL, "out must not alias y or v");
+    if (!(tau > 0) || !isfinite(tau))
+        return fail(TVREG_EINVAL, "tau must be positive and finite");
+    if (precision != TVREG_F32_RED64 && precision != TVREG_F64)
+        return fail(TVREG_EINVAL, "unknown precision %d", (int)precision);
+    const int pstride = max_reduce_blocks_vol(nx, ny, nz);
+    if (grad_dot && (!ws || ws_bytes < partial_bytes(pstride)))
+        return fail(TVREG_ENOMEM, "workspace of %zu bytes needed", partial_bytes(pstride));
+    hipStream_t st = (hipStream_t)stream;
+    double *part = grad_dot ? (double *)ws : nullptr;
+    int nb = 0;
+    if (precision == TVREG_F64)
+        TVR_HIP((launch_hessvec<double>(nx, ny, nz, tau, (const double *)y, (const double *)v,
+                                        nullptr, nullptr, 0.0, 0.0, 1.0, (double *)out, part,
+                                        pstride, st, &nb)));
+    else
+        TVR_HIP((launch_hessvec<float>(nx, ny, nz, tau, (const float *)y, (const float *)v,
+                                       nullptr, nullptr, 0.0, 0.0, 1.0, (float *)out, part,
+                                       pstride, st, &nb)));
+    if (grad_dot) {
+        SlotList sl{};
+        sl.n = 1;
+        sl.slot[0] = S_AD1;
+        sl.count[0] = nb;
+        sl.dst[0] = grad_dot;
+        TVR_HIP(launch_finalize(sl, part, pstride, st));
+    }
+    return TVREG_OK;
+}
+
 // ------------------------------------------------------------------ solver
 
 namespace {

@@ -59,6 +59,8 @@ enum Slot : int {
     S_RY2,           // sum (r_y - r_xbar)^2 (extrapolation)
     S_SS,            // |s|^2 (BB)
     S_SY,            // <s, dg> (BB)
+    S_AD1,           // <v, grad T(y)> (TV Hessian pass of the adjoint)
+    S_AD2,           // <ybar, x_new - x_old> (extrapolation adjoint)
     S_COUNT
 };
 
@@ -120,6 +122,26 @@ hipError_t launch_finalize(const SlotList &sl, const double *partials, int pstri
 // *out = 0.5 * (*r2) + alpha * (*tv)
 hipError_t launch_combine_phi(const double *r2, const double *tv, double alpha, double *out,
                               hipStream_t st);
+
+// ---------------------------------------------------- differentiated form
+// out = in + ca u + cb w + ch H_T(y) u with H_T the smoothed-TV Hessian
+// (in, w may be NULL; out may be in); slot S_AD1 = <u, grad T(y)>.
+template <typename T>
+hipError_t launch_hessvec(int nx, int ny, int nz, double tau, const T *y, const T *u, const T *in,
+                          const T *w, double ca, double cb, double ch, T *out, double *partials,
+                          int pstride, hipStream_t st, int *nblocks);
+// out = (x > 0) ? g : 0
+template <typename T>
+hipError_t launch_mask(int64_t n, const T *x, const T *g, T *out, hipStream_t st);
+// out = in + a u + b v (NULL operands are zero)
+template <typename T>
+hipError_t launch_lincomb(int64_t n, const T *in, double a, const T *u, double b, const T *v,
+                          T *out, hipStream_t st);
+// xbar_n += (1 + beta) ybar, xbar_o -= beta ybar; slot S_AD2 = <ybar, xn - xo>
+template <typename T>
+hipError_t launch_adj_extrap(int64_t n, double beta, const T *ybar, const T *xn, const T *xo,
+                             T *xbar_n, T *xbar_o, double *partials, int pstride, hipStream_t st,
+                             int *nblocks);
 
 // grid limits used to size the partial-sum buffer
 int project_blocks(const GeomDev &g);

@@ -43,6 +43,10 @@ def geoms_small():
         # any two implementations, so not tested.)
         "par_faces": synth.Geometry(6, 6, 6, np.array([0.0, 0.4]), synth.PARALLEL, 9, 7, 1.0,
                                     1.0),
+        # cone rays lying in voxel faces: at theta = 0 the u = 0 column runs in
+        # the y = 0 plane and the w = 0 row in the z = 0 plane (even sizes)
+        "cone_faces": synth.Geometry(6, 6, 6, np.array([0.0, 0.4]), synth.CONE, 9, 7, 1.0, 1.0,
+                                     30.0, 50.0),
         "one_voxel": synth.Geometry(1, 1, 1, np.array([0.3]), synth.CONE, 3, 3, 1.5, 1.5, 4.0,
                                     6.0),
         "one_ray": synth.Geometry(4, 4, 4, np.array([1.0]), synth.PARALLEL, 1, 1, 1.0, 1.0),

@@ -70,7 +70,7 @@ def test_tv_hessvec_quadratic_regime_is_laplacian():
 @pytest.fixture(scope="module")
 def small_cone():
     n = 10
-    geom = synth.cone_geometry(n, 6, 15, 15, 1.5, 4 * n, 6 * n)
+    geom = synth.cone_geometry(n, 6, 16, 16, 1.5, 4 * n, 6 * n)
     og = oracle.Geometry(geom)
     xt = synth.ellipsoid_phantom(n, 4, 7)
     b = oracle.noisy_data(og, xt, synth.unit_noise(og.proj_shape, 8), 0.01)
