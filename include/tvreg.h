@@ -97,6 +97,33 @@ tvreg_status tvreg_project(const tvreg_geometry *geom, const void *x_dev, void *
 tvreg_status tvreg_backproject(const tvreg_geometry *geom, const void *r_dev, void *x_dev,
                                void *stream);
 
+/*
+ * Stored transpose (optional).  By default the backprojector evaluates every
+ * ray/voxel length from the geometry on the fly.  A geometry can instead
+ * hold A^T in caller-owned device memory, voxel-major, built once by the
+ * same enumeration and crossing formula (each length rounded once to T), and
+ * stream it: tvreg_backproject, tvreg_objective_grad, tvreg_solve and the
+ * unrolled solver then use it.  The forward projector always walks the rays
+ * on the fly (cheaper than streaming a ray-major copy); tvreg_solve_batched
+ * always evaluates on the fly.
+ *
+ * tvreg_matrix_plan counts the entries (GPU pass; needs scratch of
+ * tvreg_matrix_scratch_bytes) and returns the bytes tvreg_matrix_attach will
+ * need and, if nnz != NULL, the number of non-zeros.  tvreg_matrix_attach
+ * builds the matrix into matrix_dev (which must stay allocated and unchanged
+ * until tvreg_matrix_detach or tvreg_destroy_geometry) and switches the
+ * geometry's backprojector to it; it synchronises `stream`.  Neither may run
+ * while another call uses the geometry.  Size: about (sizeof(T) + 4) bytes
+ * per non-zero plus slice padding (1.3e9 non-zeros, 12 GiB in FP32, for a
+ * 256^3 cone-beam scan of 60 views at 384 x 256).
+ */
+size_t tvreg_matrix_scratch_bytes(const tvreg_geometry *geom);
+tvreg_status tvreg_matrix_plan(const tvreg_geometry *geom, void *scratch_dev, size_t scratch_bytes,
+                               size_t *matrix_bytes, int64_t *nnz, void *stream);
+tvreg_status tvreg_matrix_attach(tvreg_geometry *geom, void *matrix_dev, size_t matrix_bytes,
+                                 void *stream);
+tvreg_status tvreg_matrix_detach(tvreg_geometry *geom);
+
 /* Bytes of device workspace tvreg_tv_grad and tvreg_objective_grad need. */
 size_t tvreg_tv_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
 

@@ -57,7 +57,9 @@ class _SolveInfo(ctypes.Structure):
 
 # Every symbol include/tvreg.h declares.
 EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
-           "tvreg_backproject", "tvreg_tv_workspace_bytes", "tvreg_tv_grad", "tvreg_tv_hessvec",
+           "tvreg_backproject", "tvreg_matrix_scratch_bytes", "tvreg_matrix_plan",
+           "tvreg_matrix_attach", "tvreg_matrix_detach", "tvreg_tv_workspace_bytes",
+           "tvreg_tv_grad", "tvreg_tv_hessvec",
            "tvreg_objective_workspace_bytes", "tvreg_objective_grad",
            "tvreg_solve_workspace_bytes", "tvreg_solve", "tvreg_solve_batched_workspace_bytes",
            "tvreg_solve_batched", "tvreg_unrolled_workspace_bytes", "tvreg_upn_unrolled_fwd",
@@ -83,6 +85,15 @@ def _load():
     L.tvreg_project.restype = st
     L.tvreg_backproject.argtypes = [vp, vp, vp, vp]
     L.tvreg_backproject.restype = st
+    L.tvreg_matrix_scratch_bytes.argtypes = [vp]
+    L.tvreg_matrix_scratch_bytes.restype = sz
+    L.tvreg_matrix_plan.argtypes = [vp, vp, sz, ctypes.POINTER(sz),
+                                    ctypes.POINTER(ctypes.c_int64), vp]
+    L.tvreg_matrix_plan.restype = st
+    L.tvreg_matrix_attach.argtypes = [vp, vp, sz, vp]
+    L.tvreg_matrix_attach.restype = st
+    L.tvreg_matrix_detach.argtypes = [vp]
+    L.tvreg_matrix_detach.restype = st
     L.tvreg_tv_workspace_bytes.argtypes = [ctypes.c_int32] * 3
     L.tvreg_tv_workspace_bytes.restype = sz
     L.tvreg_tv_grad.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int, ctypes.c_double, vp, vp,
@@ -189,9 +200,38 @@ class Geometry:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            _lib.tvreg_destroy_geometry(h)
+        lib_ = globals().get("_lib")  # gone already at interpreter shutdown
+        if h is not None and h.value and lib_ is not None:
+            lib_.tvreg_destroy_geometry(h)
             self.handle = None
+
+    def attach_matrix(self, device="cuda") -> int:
+        """Builds the stored system matrix (tvreg_matrix_plan / _attach) in a
+        torch allocation the geometry keeps; returns the number of non-zeros."""
+        scratch = torch.empty(_lib.tvreg_matrix_scratch_bytes(self.handle), dtype=torch.uint8,
+                              device=device)
+        nbytes = ctypes.c_size_t(0)
+        nnz = ctypes.c_int64(0)
+        stream = ctypes.c_void_p(torch.cuda.current_stream(scratch.device).cuda_stream)
+        _check(_lib.tvreg_matrix_plan(self.handle, ctypes.c_void_p(scratch.data_ptr()),
+                                      scratch.numel(), ctypes.byref(nbytes), ctypes.byref(nnz),
+                                      stream), "tvreg_matrix_plan")
+        del scratch
+        buf = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        _check(_lib.tvreg_matrix_attach(self.handle, ctypes.c_void_p(buf.data_ptr()),
+                                        buf.numel(), stream), "tvreg_matrix_attach")
+        self._matrix = buf
+        self.nnz = int(nnz.value)
+        return self.nnz
+
+    def detach_matrix(self) -> None:
+        _check(_lib.tvreg_matrix_detach(self.handle), "tvreg_matrix_detach")
+        self._matrix = None
+
+    @property
+    def matrix_bytes(self) -> int:
+        m = getattr(self, "_matrix", None)
+        return 0 if m is None else m.numel()
 
     def empty_volume(self, device="cuda"):
         return torch.empty(self.vol_shape, dtype=self.dtype, device=device)

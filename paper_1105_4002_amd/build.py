@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build", "tvreg")
 LIB_PATH = os.path.join(PKG, "libtvreg.so")
-SOURCES = ["project.hip", "backproject.hip", "stencil.hip", "adjoint.hip", "batch.hip",
+SOURCES = ["project.hip", "backproject.hip", "matrix.hip", "stencil.hip", "adjoint.hip", "batch.hip",
            "unrolled.hip", "api.hip"]
 
 ARCH = "gfx950"

@@ -905,6 +905,155 @@ extern "C" tvreg_status tvreg_solve(const tvreg_geometry *G, const void *b,
     return solve_impl<float>(G, (const float *)b, p, (float *)x, (char *)ws, info, st);
 }
 
+// ------------------------------------------------------ stored system matrix
+
+namespace {
+
+struct MatLayout {
+    int64_t sv, ev;
+    size_t off_v, w_v, cnt_v, val_v, idx_v, total;
+};
+
+// fixed part (slice table and counts), then the entries once counted
+MatLayout mat_layout(const tvreg_geometry *G, int64_t ev)
+{
+    MatLayout L{};
+    L.sv = (G->N + 63) / 64;
+    L.ev = ev;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    L.off_v = take(sizeof(int64_t) * (size_t)L.sv);
+    L.w_v = take(sizeof(int32_t) * (size_t)L.sv);
+    L.cnt_v = take(sizeof(int32_t) * (size_t)G->N);
+    L.val_v = take(elem_size(G->prec) * (size_t)ev);
+    L.idx_v = take(sizeof(int32_t) * (size_t)ev);
+    L.total = off;
+    return L;
+}
+
+// counts and slice widths into the given buffers, then the slice offsets
+// (host) and the entry total (with padding)
+tvreg_status count_entries(const tvreg_geometry *G, int32_t *cnt_v, int32_t *w_v, hipStream_t st,
+                           std::vector<int64_t> &off_v, int64_t &ev, int64_t *nnz)
+{
+    GeomDev g = G->g;
+    g.mat = MatDev{};
+    const int64_t sv = (G->N + 63) / 64;
+    TVR_HIP(launch_matrix_count(g, cnt_v, st));
+    TVR_HIP(launch_slice_widths(cnt_v, G->N, w_v, st));
+    std::vector<int32_t> wv((size_t)sv);
+    TVR_HIP(hipMemcpyAsync(wv.data(), w_v, sizeof(int32_t) * wv.size(), hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> cv;
+    if (nnz) {
+        cv.resize((size_t)G->N);
+        TVR_HIP(hipMemcpyAsync(cv.data(), cnt_v, sizeof(int32_t) * cv.size(),
+                               hipMemcpyDeviceToHost, st));
+    }
+    TVR_HIP(hipStreamSynchronize(st));
+    off_v.resize((size_t)sv);
+    ev = 0;
+    for (int64_t s = 0; s < sv; ++s) {
+        off_v[s] = ev;
+        ev += 64 * (int64_t)wv[s];
+    }
+    if (nnz) {
+        int64_t t = 0;
+        for (int32_t c : cv)
+            t += c;
+        *nnz = t;
+    }
+    return TVREG_OK;
+}
+
+}  // namespace
+
+extern "C" size_t tvreg_matrix_scratch_bytes(const tvreg_geometry *G)
+{
+    if (!G)
+        return 0;
+    return mat_layout(G, 0).val_v;  // the fixed part: slice table and counts
+}
+
+extern "C" tvreg_status tvreg_matrix_plan(const tvreg_geometry *G, void *scratch,
+                                          size_t scratch_bytes, size_t *matrix_bytes,
+                                          int64_t *nnz, void *stream)
+{
+    g_err.clear();
+    if (!G || !matrix_bytes)
+        return fail(TVREG_EINVAL, "NULL geometry or output");
+    const MatLayout L0 = mat_layout(G, 0);
+    if (!scratch || scratch_bytes < L0.val_v)
+        return fail(TVREG_ENOMEM, "scratch of %zu bytes needed", L0.val_v);
+    DeviceGuard dg(G->device);
+    if (!dg.ok)
+        return fail(TVREG_EDEVICE, "cannot select device %d", G->device);
+    char *b = (char *)scratch;
+    std::vector<int64_t> off_v;
+    int64_t ev = 0;
+    TVR_TRY(count_entries(G, (int32_t *)(b + L0.cnt_v), (int32_t *)(b + L0.w_v),
+                          (hipStream_t)stream, off_v, ev, nnz));
+    *matrix_bytes = mat_layout(G, ev).total;
+    return TVREG_OK;
+}
+
+extern "C" tvreg_status tvreg_matrix_attach(tvreg_geometry *G, void *matrix, size_t matrix_bytes,
+                                            void *stream)
+{
+    g_err.clear();
+    if (!G || !matrix)
+        return fail(TVREG_EINVAL, "NULL geometry or matrix buffer");
+    DeviceGuard dg(G->device);
+    if (!dg.ok)
+        return fail(TVREG_EDEVICE, "cannot select device %d", G->device);
+    hipStream_t st = (hipStream_t)stream;
+    const MatLayout L0 = mat_layout(G, 0);
+    if (matrix_bytes < L0.val_v)
+        return fail(TVREG_ENOMEM, "matrix buffer smaller than its fixed part (%zu bytes)",
+                    L0.val_v);
+    char *b = (char *)matrix;
+    std::vector<int64_t> off_v;
+    int64_t ev = 0;
+    TVR_TRY(count_entries(G, (int32_t *)(b + L0.cnt_v), (int32_t *)(b + L0.w_v), st, off_v, ev,
+                          nullptr));
+    const MatLayout L = mat_layout(G, ev);
+    if (matrix_bytes < L.total)
+        return fail(TVREG_ENOMEM, "matrix of %zu bytes needed", L.total);
+    TVR_HIP(hipMemcpyAsync(b + L.off_v, off_v.data(), sizeof(int64_t) * off_v.size(),
+                           hipMemcpyHostToDevice, st));
+    MatDev M{};
+    M.present = 1;
+    M.sv = L.sv;
+    M.off_v = (const int64_t *)(b + L.off_v);
+    M.w_v = (const int32_t *)(b + L.w_v);
+    M.cnt_v = (const int32_t *)(b + L.cnt_v);
+    M.val_v = b + L.val_v;
+    M.idx_v = (const int32_t *)(b + L.idx_v);
+    GeomDev g = G->g;
+    g.mat = M;
+    if (G->prec == TVREG_F64)
+        TVR_HIP(launch_matrix_fill<double>(g, (double *)(b + L.val_v), (int32_t *)(b + L.idx_v),
+                                           st));
+    else
+        TVR_HIP(launch_matrix_fill<float>(g, (float *)(b + L.val_v), (int32_t *)(b + L.idx_v),
+                                          st));
+    TVR_HIP(hipStreamSynchronize(st));
+    G->g.mat = M;
+    return TVREG_OK;
+}
+
+extern "C" tvreg_status tvreg_matrix_detach(tvreg_geometry *G)
+{
+    g_err.clear();
+    if (!G)
+        return fail(TVREG_EINVAL, "NULL geometry");
+    G->g.mat = MatDev{};
+    return TVREG_OK;
+}
+
 extern "C" void tvreg_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);

@@ -253,6 +253,7 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         BatchProblem<T> &P = hp[i];
         memset(&P, 0, sizeof(P));
         P.g = G->g;
+        P.g.mat = MatDev{};  // grouped launches evaluate the operators on the fly
         P.N = (int)G->N;
         P.m = (int)G->m;
         P.nb_vox = max_reduce_blocks_vol(G->g.nx, G->g.ny, G->g.nz);
@@ -286,7 +287,7 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         P.state = B_RUNNING;
         P.first = 1;
         P.grad_evals = 1;
-        const GeomDev &g = G->g;
+        const GeomDev &g = P.g;
         TVR_HIP(launch_clip<T>(G->N, (const T *)x_io[i], P.X, st));
         TVR_HIP(launch_transpose_xy<T>(g.nx, g.ny, g.nz, P.X, P.XT, st));
         TVR_HIP(launch_project<T>(g, P.X, P.XT, P.b, P.RX, nullptr, P.part, P.pstride, st,

@@ -1,0 +1,108 @@
+// Siddon walk of the projector: the slab clip of a ray against the volume
+// and the voxel-to-voxel traversal, both from the ray tables' crossing
+// formula plane_t, with a visitor per voxel segment.
+#pragma once
+
+#include "tvreg_internal.hpp"
+
+namespace tvr {
+
+// Slab entry/exit of the ray with the volume along one axis; a ray parallel
+// to the axis (invD = 0) is inside iff S lies in the half-open range.
+__device__ __forceinline__ void slab(double lo, double hi, double S, double invD, double o,
+                                     double &tmin, double &tmax, bool &hit)
+{
+    if (invD != 0.0) {
+        const double t0 = plane_t(lo, invD, o), t1 = plane_t(hi, invD, o);
+        tmin = fmax(tmin, fmin(t0, t1));
+        tmax = fmin(tmax, fmax(t0, t1));
+    } else {
+        hit = hit && (S >= lo) && (S < hi);
+    }
+}
+
+// Visits the ray's voxels in order, calling visit(index, dt) with dt the
+// parameter length inside the voxel (multiply by |D| for the length; dt may be
+// 0 where two crossings coincide).  Walks voxel to voxel: the next
+// crossing of each axis is plane_t(X) of the next plane X, the segment ends
+// at the nearest one, and every axis whose crossing is reached advances (a
+// tie of two axes is one crossing, so no zero-length piece is visited).
+// The exit crossing of each axis is computed with the same formula as the
+// slab exit, so no index leaves the volume before t reaches tmax.
+// The volume is read through strides (sx, sy) so that a y-fastest copy can
+// serve views whose rays run mostly along x (adjacent detector columns then
+// touch adjacent addresses).
+template <bool CONE, class Visit>
+__device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry &ce,
+                                               const RowEntry &re, int sx, int sy, Visit &&visit)
+{
+    const double lox = -g.hx, loy = -g.hy, loz = -g.hz;
+    double tmin = CONE ? 0.0 : -INFINITY;
+    double tmax = CONE ? 1.0 : INFINITY;
+    bool hit = true;
+    slab(lox, g.hx, ce.Sx, ce.invDx, ce.ox, tmin, tmax, hit);
+    slab(loy, g.hy, ce.Sy, ce.invDy, ce.oy, tmin, tmax, hit);
+    slab(loz, g.hz, re.Sz, re.invDz, re.oz, tmin, tmax, hit);
+    if (!hit || !(tmax > tmin))
+        return;
+
+    // entry voxel (an axis the ray runs parallel to keeps its coordinate;
+    // the clamp absorbs rounding at the entry face)
+    int ix = (int)floor((ce.invDx != 0.0 ? ce.Sx + tmin * ce.Dx : ce.Sx) - lox);
+    int iy = (int)floor((ce.invDy != 0.0 ? ce.Sy + tmin * ce.Dy : ce.Sy) - loy);
+    int iz = (int)floor((re.invDz != 0.0 ? re.Sz + tmin * re.Dz : re.Sz) - loz);
+    ix = min(max(ix, 0), g.nx - 1);
+    iy = min(max(iy, 0), g.ny - 1);
+    iz = min(max(iz, 0), g.nz - 1);
+
+    const bool px = ce.Dx > 0.0, py = ce.Dy > 0.0, pz = re.Dz > 0.0;
+    const double sxd = px ? 1.0 : -1.0, syd = py ? 1.0 : -1.0, szd = pz ? 1.0 : -1.0;
+    double Xn = lox + (double)(ix + (px ? 1 : 0));
+    double Yn = loy + (double)(iy + (py ? 1 : 0));
+    double Zn = loz + (double)(iz + (pz ? 1 : 0));
+    double tnx = ce.invDx != 0.0 ? plane_t(Xn, ce.invDx, ce.ox) : INFINITY;
+    double tny = ce.invDy != 0.0 ? plane_t(Yn, ce.invDy, ce.oy) : INFINITY;
+    double tnz = re.invDz != 0.0 ? plane_t(Zn, re.invDz, re.oz) : INFINITY;
+    const int sz = g.nx * g.ny;
+    const int stx = px ? sx : -sx;
+    const int sty = py ? sy : -sy;
+    const int stz = pz ? sz : -sz;
+    const unsigned last = (unsigned)(g.nx * g.ny * g.nz - 1);
+    int idx = ix * sx + iy * sy + iz * sz;
+
+    double t = tmin;
+    const int cap = g.nx + g.ny + g.nz + 2;  // hard bound on the number of voxels
+    for (int it = 0; it < cap; ++it) {
+        const double tn = fmin(fmin(tnx, tny), fmin(tnz, tmax));
+        visit(min((unsigned)idx, last), fmax(tn - t, 0.0));
+        t = tn;
+        if (!(t < tmax))
+            break;
+        const bool ax = tnx <= tn, ay = tny <= tn, az = tnz <= tn;
+        idx += (ax ? stx : 0) + (ay ? sty : 0) + (az ? stz : 0);
+        const double Xa = Xn + sxd, Ya = Yn + syd, Za = Zn + szd;
+        const double ta = plane_t(Xa, ce.invDx, ce.ox);
+        const double tb = plane_t(Ya, ce.invDy, ce.oy);
+        const double tc = plane_t(Za, re.invDz, re.oz);
+        Xn = ax ? Xa : Xn;
+        Yn = ay ? Ya : Yn;
+        Zn = az ? Za : Zn;
+        tnx = ax ? ta : tnx;
+        tny = ay ? tb : tny;
+        tnz = az ? tc : tnz;
+    }
+}
+
+// Sum of dt * x along the ray (the projector's ray sum before |D|).
+template <typename T, bool CONE>
+__device__ __forceinline__ double ray_walk(const GeomDev &g, const T *__restrict__ x,
+                                           const ColEntry &ce, const RowEntry &re, int sx,
+                                           int sy)
+{
+    double acc = 0.0;
+    ray_walk_visit<CONE>(g, ce, re, sx, sy,
+                         [&](unsigned idx, double dt) { acc = fma(dt, (double)x[idx], acc); });
+    return acc;
+}
+
+}  // namespace tvr

@@ -28,6 +28,19 @@ __host__ __device__ __forceinline__ double plane_t(double X, double invD, double
     return fma(X, invD, o);
 }
 
+// Optional stored transpose A^T in SELL-64 form (slices of 64 consecutive
+// voxels; entry k of lane l of slice s at off[s] + 64 k + l): values
+// a_ij = length |D_i| as T, ray indices int32.
+struct MatDev {
+    int present;                     // 0: A^T evaluated on the fly
+    int64_t sv;                      // slices of voxels
+    const int64_t *off_v;            // first entry of each slice
+    const int32_t *w_v;              // slice widths (max entries of a lane)
+    const int32_t *cnt_v;            // entries of each voxel
+    const void *val_v;               // a_ij
+    const int32_t *idx_v;            // ray index of each entry
+};
+
 struct GeomDev {
     int nx, ny, nz;
     int nviews, cols, rows;
@@ -40,6 +53,7 @@ struct GeomDev {
     const ColEntry *col;       // [nviews * cols]
     const RowEntry *row;       // [rows]
     const double *dnorm;       // |D|: cone [rows * cols], parallel [nviews]
+    MatDev mat;                // stored A^T when present
 };
 
 // Double-precision reduction results live in fixed slots; every kernel that
@@ -122,6 +136,19 @@ hipError_t launch_finalize(const SlotList &sl, const double *partials, int pstri
 // *out = 0.5 * (*r2) + alpha * (*tv)
 hipError_t launch_combine_phi(const double *r2, const double *tv, double alpha, double *out,
                               hipStream_t st);
+
+// ------------------------------------------------- stored system matrix
+// x = A^T r from the stored transpose; called by launch_backproject when
+// g.mat.present.
+template <typename T>
+hipError_t launch_backproject_matrix(const GeomDev &g, const T *r, T *out, hipStream_t st);
+// entries per voxel (the counting pass of the build)
+hipError_t launch_matrix_count(const GeomDev &g, int32_t *cnt_v, hipStream_t st);
+// slice widths w[s] = max of cnt over the slice's 64 lanes
+hipError_t launch_slice_widths(const int32_t *cnt, int64_t n, int32_t *w, hipStream_t st);
+// fills values and ray indices at the offsets of g.mat
+template <typename T>
+hipError_t launch_matrix_fill(const GeomDev &g, T *val_v, int32_t *idx_v, hipStream_t st);
 
 // ---------------------------------------------------- differentiated form
 // out = in + ca u + cb w + ch H_T(y) u with H_T the smoothed-TV Hessian
