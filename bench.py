@@ -5,16 +5,19 @@ Workload (synthetic, seeded): 256^3 voxels, cone beam with 60 views over
 360 degrees, flat detector 384 x 256 at pitch 1.5, source 1024 and detector
 1536 from the centre, 24-ellipsoid phantom, 0.5 % Gaussian noise,
 alpha = 3e-3, tau = 1e-4.  Method: UPN (Alg. 3) with FP32 vectors and FP64
-reductions.
+reductions; the backprojector streams the stored voxel-major A^T (built
+before the timed region, its size and build time reported), the projector
+walks the rays on the fly.
 
-A "step" is one UPN iteration: gradient at y (gather backprojection + TV
-stencil), projected trial step(s) with the projector's fused residual, the
-scalar control and the extrapolation.  `value` is gradient evaluations per
-second over exactly --steps iterations (inputs resident in HBM).  Beside it:
-the time to a 1e-6 relative gradient-map tolerance from x0 = 0, the live
-per-kernel durations (HIP events around each launch of the timed solve), the
-dominant kernel's roofline, and the FP64 CPU oracle's gradient-evaluation
-rate on the host cores.
+A "step" is one UPN iteration: gradient at y (backprojection + TV stencil),
+projected trial step(s) with the projector's fused residual, the scalar
+control and the extrapolation.  `value` is gradient evaluations per second
+over exactly --steps iterations (inputs resident in HBM).  Beside it: the
+same rate with every operator on the fly, the time to a 1e-6 relative
+gradient-map tolerance from x0 = 0, the live per-kernel durations (HIP events
+around each launch of the timed solve), the dominant kernel's roofline, the
+32-problem batch and the differentiated 64^3 form, and the FP64 CPU oracle's
+gradient-evaluation rate on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--fp64] [--gp64-iters N]
 """
@@ -38,14 +41,18 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_model(name: str, N: int, m: int, nnz: int, es: int):
-    """Algorithmic work of one launch of each solver kernel (FP32 storage,
-    es = 4 bytes).  Returns (bound, amount, unit, peak)."""
+def kernel_model(name: str, N: int, m: int, nnz: int, es: int, stored: bool):
+    """Algorithmic work of one launch of each solver kernel (es = bytes per
+    stored value).  Returns (bound, amount, unit, peak)."""
     if name == "project":
         # 7 flops per (ray, voxel) step of the walk: 3-way min, length,
         # accumulate (FMA = 2), next-crossing update (FMA = 2)
         return "alu", 7.0 * nnz, "TFLOP/s", FP64_VEC_PEAK
     if name == "backproject":
+        if stored:
+            # every non-zero streamed once (value + int32 ray index), r read
+            # once, the volume written once
+            return "hbm", (es + 4.0) * nnz + es * (m + N), "GB/s", HBM_PEAK
         # 10 flops per (voxel, ray) pair: two z-plane parameters (2 FMA),
         # max, min, length, |D| scale, accumulate (FMA)
         return "alu", 10.0 * nnz, "TFLOP/s", FP64_VEC_PEAK
@@ -60,6 +67,71 @@ def kernel_model(name: str, N: int, m: int, nnz: int, es: int):
     raise KeyError(name)
 
 
+def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool):
+    """The 32-problem batch (uneven sizes, views and alphas), FP32 UPN to tol:
+    one tvreg_solve_batched call, and optionally the same problems one by one."""
+    ws_ = synth.cfg_batch()
+    geoms, bs = [], []
+    for w in ws_:
+        G64 = tv.Geometry(w.geom, tv.F64)
+        ax = tv.project(G64, torch.from_numpy(w.phantom()).to(dev))
+        sigma = w.eta * torch.linalg.vector_norm(ax).item() / math.sqrt(ax.numel())
+        bs.append((ax + sigma * torch.from_numpy(w.unit_noise()).to(dev)).float().contiguous())
+        del G64, ax
+        geoms.append(tv.Geometry(w.geom, tv.F32))
+    params = [dict(method=tv.UPN, alpha=w.alpha, tau=w.tau, eps=tol, max_iter=max_iter)
+              for w in ws_]
+    ws = tv.solve_batched_workspace(geoms, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos, status = tv.solve_batched(geoms, bs, params, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"problems": len(geoms), "voxels": int(sum(g.N for g in geoms)),
+           "batched_seconds": round(dt, 3), "status": int(status),
+           "iters_max": max(i["iters"] for i in infos),
+           "grad_evals": int(sum(i["grad_evals"] for i in infos)),
+           "converged": int(sum(1 for i in infos if i["stop_reason"] == tv.OK))}
+    if sequential:
+        t0 = time.perf_counter()
+        for G, b, p in zip(geoms, bs, params):
+            tv.solve(G, b, **p)
+        torch.cuda.synchronize()
+        out["sequential_seconds"] = round(time.perf_counter() - t0, 3)
+        out["speedup"] = round(out["sequential_seconds"] / dt, 3)
+    return out
+
+
+def unrolled_leg(tv, synth, torch, dev, reps: int = 3):
+    """The differentiated form: 64^3, cone beam, 30 views, 96 x 96, K = 30
+    unrolled UPN steps, forward + reverse pass in FP32 (checkpoints every 5)."""
+    w = synth.cfg_unrolled()
+    G = tv.Geometry(w.geom, tv.F32)
+    G64 = tv.Geometry(w.geom, tv.F64)
+    xt = torch.from_numpy(w.phantom()).to(dev)
+    ax = tv.project(G64, xt)
+    sigma = w.eta * torch.linalg.vector_norm(ax).item() / math.sqrt(ax.numel())
+    b = (ax + sigma * torch.from_numpy(w.unit_noise()).to(dev)).float().contiguous()
+    xt32 = xt.float()
+    tape = tv.unrolled_workspace(G, 30, 5, dev)
+    xK, tape, L = tv.upn_unrolled_fwd(G, b, 30, w.alpha, tau=w.tau, tape=tape)
+    tv.upn_unrolled_bwd(G, b, tape, 2.0 * (xK - xt32))
+    torch.cuda.synchronize()
+    tf = tb = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        xK, tape, _ = tv.upn_unrolled_fwd(G, b, 30, w.alpha, tau=w.tau, L_replay=L, tape=tape)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tv.upn_unrolled_bwd(G, b, tape, 2.0 * (xK - xt32))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf += t1 - t0
+        tb += t2 - t1
+    return {"K": 30, "ckpt_every": 5, "forward_ms": round(1e3 * tf / reps, 2),
+            "reverse_ms": round(1e3 * tb / reps, 2)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +144,12 @@ def main() -> int:
     ap.add_argument("--gp64-iters", type=int, default=0,
                     help="also run GP in FP64 for up to this many iterations")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-matrix", action="store_true",
+                    help="evaluate A^T on the fly in the headline solve")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the on-the-fly, batch and differentiated legs")
+    ap.add_argument("--batch-seq", action="store_true",
+                    help="also solve the batch problems one by one")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -107,6 +185,16 @@ def main() -> int:
     torch.cuda.synchronize()
     ws32 = tv.solve_workspace(G32, tv.UPN)
     common = dict(alpha=w.alpha, tau=w.tau)
+    stored = not args.no_matrix
+    matrix = None
+    if stored:
+        log("building the stored A^T")
+        torch.cuda.synchronize()
+        m0 = time.perf_counter()
+        mnnz = G32.attach_matrix()
+        torch.cuda.synchronize()
+        matrix = {"gib": round(G32.matrix_bytes / 2**30, 3), "nnz": mnnz,
+                  "build_s": round(time.perf_counter() - m0, 3)}
 
     log(f"warmup: {args.warmup} UPN iterations")
     xw, iw, _ = tv.solve(G32, b32, method=tv.UPN, eps=0.0, max_iter=max(args.warmup, 1),
@@ -132,13 +220,13 @@ def main() -> int:
     kernels = {}
     for name, (cnt, ms) in stats.items():
         if cnt:
-            bound, amount, unit, peak = kernel_model(name, N, m, nnz, 4)
+            bound, amount, unit, peak = kernel_model(name, N, m, nnz, 4, stored)
             avg = ms / cnt / 1e3
             kernels[name] = {"launches": cnt, "avg_ms": round(ms / cnt, 4),
                              "total_ms": round(ms, 3), "bound": bound,
                              "frac": round(amount / avg / peak, 4)}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-    bound, amount, unit, peak = kernel_model(dom, N, m, nnz, 4)
+    bound, amount, unit, peak = kernel_model(dom, N, m, nnz, 4, stored)
     avg_s = kernels[dom]["avg_ms"] / 1e3
     scale = 1e12 if unit == "TFLOP/s" else 1e9
     roofline = {"kernel": dom, "bound": bound, "achieved": round(amount / avg_s / scale, 3),
@@ -154,14 +242,33 @@ def main() -> int:
         "config": {"workload": "cone256: 256^3 voxels, cone beam 60 views/360 deg, detector "
                                "384x256 @1.5, R=1024, SDD=1536, 24 ellipsoids, 0.5% noise, "
                                "alpha=3e-3, tau=1e-4; UPN, FP32 vectors + FP64 reductions",
+                   "operators": ("projector on the fly, backprojector from the stored A^T"
+                                 if stored else "both on the fly"),
                    "global_batch": 1, "parallelism": "single GPU"},
         "roofline": roofline,
         "kernels": kernels,
     }
+    if matrix:
+        result["stored_transpose"] = matrix
+
+    if stored and not args.no_legs:
+        log(f"same solve with every operator on the fly: {args.steps} UPN iterations")
+        G32.detach_matrix()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, i0, _ = tv.solve(G32, b32, method=tv.UPN, eps=0.0, max_iter=args.steps, x0=xw,
+                            L_bar=iw["L"], workspace=ws32, **common)
+        torch.cuda.synchronize()
+        d0 = time.perf_counter() - t0
+        result["on_the_fly"] = {"value": round(i0["grad_evals"] / d0, 3),
+                                "ms_per_step": round(1e3 * d0 / args.steps, 4)}
+        G32.attach_matrix()
 
     if not args.no_tol:
         for label, G, bb in [("f32", G32, b32)] + ([("f64", G64, b64)] if args.fp64 else []):
             log(f"time to tolerance {args.tol:g}: UPN {label}")
+            if label == "f64" and stored:
+                G.attach_matrix()
             ws = ws32 if label == "f32" else tv.solve_workspace(G, tv.UPN)
             torch.cuda.synchronize()
             s0 = time.perf_counter()
@@ -177,6 +284,15 @@ def main() -> int:
             log(f"  {dt:.2f} s, {info['iters']} iterations, status {info['stop_reason']}")
             if label == "f64":
                 del ws
+                if stored:
+                    G.detach_matrix()
+    if not args.no_legs:
+        log("32-problem batch, FP32 UPN to 1e-6")
+        result["batch32"] = batch_leg(tv, synth, torch, dev, 1e-6, 5000, args.batch_seq)
+        log(f"  {result['batch32']}")
+        log("differentiated form: 64^3, K = 30")
+        result["unrolled64"] = unrolled_leg(tv, synth, torch, dev)
+        log(f"  {result['unrolled64']}")
     if args.gp64_iters > 0:
         log(f"GP FP64 for up to {args.gp64_iters} iterations")
         ws = tv.solve_workspace(G64, tv.GP)
