@@ -150,6 +150,9 @@ def main() -> int:
                     help="skip the on-the-fly, batch and differentiated legs")
     ap.add_argument("--batch-seq", action="store_true",
                     help="also solve the batch problems one by one")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device to device (a plain copy of known size that "
+                         "scales hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -166,6 +169,12 @@ def main() -> int:
     import synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(2**28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = synth.cfg_cone256()
     g = w.geom
     N, m = g.n_voxels, g.n_rays

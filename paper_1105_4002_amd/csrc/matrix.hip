@@ -144,9 +144,14 @@ __global__ __launch_bounds__(MB) void spmv_voxels_kernel(GeomDev g, const T *__r
     const int32_t *__restrict__ idx = g.mat.idx_v + g.mat.off_v[s] + (j & 63);
     const int w = j < N ? g.mat.w_v[s] : 0;  // lanes past the last voxel hold no entries
     double acc = 0.0;
+    // the matrix is read once per product: non-temporal loads keep it from
+    // evicting r, which every voxel gathers from
 #pragma unroll 8
-    for (int k = 0; k < w; ++k)
-        acc = fma((double)val[64 * k], (double)r[idx[64 * k]], acc);
+    for (int k = 0; k < w; ++k) {
+        const T a = __builtin_nontemporal_load(val + 64 * k);
+        const int32_t i = __builtin_nontemporal_load(idx + 64 * k);
+        acc = fma((double)a, (double)r[i], acc);
+    }
     if (j < N)
         out[j] = (T)acc;
 }

@@ -63,8 +63,29 @@ __device__ __forceinline__ C huber_bregman(C a0, C a1, C a2, C b0, C b1, C b2, C
     return C(0.5) * (e0 * e0 + e1 * e1 + e2 * e2) * itau;
 }
 
+// One z-plane of a volume staged in LDS: columns [x0 - o, x0 - o + W) x
+// rows [y0 - o, y0 - o + H) of plane z, zero outside the volume; all the
+// block's threads take part.
+template <typename T, int H, int W>
+__device__ __forceinline__ void stage_plane(const T *__restrict__ v, int nx, int ny, int x0,
+                                            int y0, int o, int z, T (&tile)[H][W])
+{
+    const size_t plane = (size_t)nx * ny * z;
+    for (int e = thread_linear_id(); e < H * W; e += VX * VY) {
+        const int ty = e / W, tx = e - ty * W;
+        const int gx = x0 - o + tx, gy = y0 - o + ty;
+        tile[ty][tx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                           ? v[plane + (size_t)gy * nx + gx]
+                           : T(0);
+    }
+}
+
 // gout = (gin ? gin : 0) + alpha grad T(y); with partials also the sums
-// T(y) and, with xref, Bregman_T(xref, y) and |xref - y|^2.
+// T(y) and, with xref, Bregman_T(xref, y) and |xref - y|^2.  The block's
+// 64 x 4 columns march up VZ planes; each plane of y (with a one-voxel halo
+// on the low sides for the left and front neighbours' terms and on the high
+// sides for the forward differences) and of xref is staged once in LDS,
+// double-buffered against the next plane, so every neighbour is an LDS read.
 template <typename T>
 __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, double alpha,
                                          const T *__restrict__ y, const T *__restrict__ xref,
@@ -72,82 +93,94 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
                                          double *__restrict__ partials, int pstride, int bx,
                                          int by, int bz, int bid)
 {
-    const int ix = bx * VX + threadIdx.x;
-    const int iy = by * VY + threadIdx.y;
+    __shared__ T ys[2][VY + 2][VX + 2];  // x in [x0 - 1, x0 + VX], y in [y0 - 1, y0 + VY]
+    __shared__ T xs[2][VY + 1][VX + 1];  // x in [x0, x0 + VX], y in [y0, y0 + VY]
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x0 = bx * VX, y0 = by * VY;
+    const int ix = x0 + tx, iy = y0 + ty;
     const int z0 = bz * VZ;
     const int z1 = min(z0 + VZ, nz);
+    const bool active = ix < nx && iy < ny;
     double red[3] = {0.0, 0.0, 0.0};
-    if (ix < nx && iy < ny) {
-        const T ct = (T)tau, itau = T(1) / ct;
-        const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-        const bool hx = ix + 1 < nx, hy = iy + 1 < ny, lx = ix > 0, ly = iy > 0;
-        // z component of q at the voxel below the chunk
-        T qz_prev = T(0);
-        if (z0 > 0) {
-            const size_t jb = (size_t)ix + sy * iy + sz * (z0 - 1);
-            const T yb = y[jb];
-            const T dx = hx ? y[jb + 1] - yb : T(0);
-            const T dy = hy ? y[jb + sy] - yb : T(0);
-            const T dz = y[jb + sz] - yb;
-            qz_prev = dz * SM<T>::inv_clamped(dx * dx + dy * dy + dz * dz, ct, itau);
+    const T ct = (T)tau, itau = T(1) / ct;
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    const bool hx = ix + 1 < nx, hy = iy + 1 < ny, lx = ix > 0, ly = iy > 0;
+    // z component of q at the voxel below the chunk
+    T qz_prev = T(0);
+    if (active && z0 > 0) {
+        const size_t jb = (size_t)ix + sy * iy + sz * (z0 - 1);
+        const T yb = y[jb];
+        const T dx = hx ? y[jb + 1] - yb : T(0);
+        const T dy = hy ? y[jb + sy] - yb : T(0);
+        const T dz = y[jb + sz] - yb;
+        qz_prev = dz * SM<T>::inv_clamped(dx * dx + dy * dy + dz * dz, ct, itau);
+    }
+    int cur = 0;
+    stage_plane(y, nx, ny, x0, y0, 1, z0, ys[0]);
+    if (xref)
+        stage_plane(xref, nx, ny, x0, y0, 0, z0, xs[0]);
+    for (int z = z0; z < z1; ++z) {
+        const int nxt = cur ^ 1;
+        const bool hz = z + 1 < nz;
+        if (hz) {  // block-uniform
+            stage_plane(y, nx, ny, x0, y0, 1, z + 1, ys[nxt]);
+            if (xref)
+                stage_plane(xref, nx, ny, x0, y0, 0, z + 1, xs[nxt]);
         }
-        for (int z = z0; z < z1; ++z) {
-            const size_t j = (size_t)ix + sy * iy + sz * z;
-            const bool hz = z + 1 < nz;
-            const T yj = y[j];
-            const T dx = hx ? y[j + 1] - yj : T(0);
-            const T dy = hy ? y[j + sy] - yj : T(0);
-            const T dz = hz ? y[j + sz] - yj : T(0);
+        __syncthreads();
+        if (active) {
+            const T(&Y)[VY + 2][VX + 2] = ys[cur];
+            const T(&Yn)[VY + 2][VX + 2] = ys[nxt];
+            const int cx = tx + 1, cy = ty + 1;
+            const T yj = Y[cy][cx];
+            const T dx = hx ? Y[cy][cx + 1] - yj : T(0);
+            const T dy = hy ? Y[cy + 1][cx] - yj : T(0);
+            const T dz = hz ? Yn[cy][cx] - yj : T(0);
             const T d2 = dx * dx + dy * dy + dz * dz;
             const T inv = SM<T>::inv_clamped(d2, ct, itau);
             T gsum = -(dx + dy + dz) * inv + qz_prev;
             qz_prev = dz * inv;
-            if (lx) {  // x component of q at the voxel on the left
-                const size_t k = j - 1;
-                const T yk = y[k];
+            {  // x component of q at the voxel on the left
+                const T yk = Y[cy][cx - 1];
                 const T ex = yj - yk;
-                const T ey = hy ? y[k + sy] - yk : T(0);
-                const T ez = hz ? y[k + sz] - yk : T(0);
-                gsum += ex * SM<T>::inv_clamped(ex * ex + ey * ey + ez * ez, ct, itau);
+                const T ey = hy ? Y[cy + 1][cx - 1] - yk : T(0);
+                const T ez = hz ? Yn[cy][cx - 1] - yk : T(0);
+                const T t = ex * SM<T>::inv_clamped(ex * ex + ey * ey + ez * ez, ct, itau);
+                gsum += lx ? t : T(0);
             }
-            if (ly) {  // y component of q at the voxel in front
-                const size_t k = j - sy;
-                const T yk = y[k];
-                const T ex = hx ? y[k + 1] - yk : T(0);
+            {  // y component of q at the voxel in front
+                const T yk = Y[cy - 1][cx];
+                const T ex = hx ? Y[cy - 1][cx + 1] - yk : T(0);
                 const T ey = yj - yk;
-                const T ez = hz ? y[k + sz] - yk : T(0);
-                gsum += ey * SM<T>::inv_clamped(ex * ex + ey * ey + ez * ez, ct, itau);
+                const T ez = hz ? Yn[cy - 1][cx] - yk : T(0);
+                const T t = ey * SM<T>::inv_clamped(ex * ex + ey * ey + ez * ez, ct, itau);
+                gsum += ly ? t : T(0);
             }
+            const size_t j = (size_t)ix + sy * iy + sz * z;
             if (gout)
                 gout[j] = gin ? (T)((double)gin[j] + alpha * (double)gsum)
                               : (T)(alpha * (double)gsum);
             if (partials) {
                 red[0] += (double)huber_c<T>(d2, ct, itau);
                 if (xref) {
-                    const T xj = xref[j];
+                    const T(&X)[VY + 1][VX + 1] = xs[cur];
+                    const T xj = X[ty][tx];
                     const T ej = xj - yj;
-                    T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
-                    if (hx) {
-                        const T xn = xref[j + 1];
-                        a0 = xn - xj;
-                        e0 = (xn - y[j + 1]) - ej;
-                    }
-                    if (hy) {
-                        const T xn = xref[j + sy];
-                        a1 = xn - xj;
-                        e1 = (xn - y[j + sy]) - ej;
-                    }
-                    if (hz) {
-                        const T xn = xref[j + sz];
-                        a2 = xn - xj;
-                        e2 = (xn - y[j + sz]) - ej;
-                    }
+                    const T xa = X[ty][tx + 1], xb = X[ty + 1][tx], xc = xs[nxt][ty][tx];
+                    const T a0 = hx ? xa - xj : T(0);
+                    const T e0 = hx ? (xa - Y[cy][cx + 1]) - ej : T(0);
+                    const T a1 = hy ? xb - xj : T(0);
+                    const T e1 = hy ? (xb - Y[cy + 1][cx]) - ej : T(0);
+                    const T a2 = hz ? xc - xj : T(0);
+                    const T e2 = hz ? (xc - Yn[cy][cx]) - ej : T(0);
                     red[1] += (double)huber_bregman<T>(a0, a1, a2, dx, dy, dz, e0, e1, e2, ct, itau);
                     const double ed = (double)xj - (double)yj;
                     red[2] += ed * ed;
                 }
             }
         }
+        __syncthreads();  // the next plane overwrites this one's buffer
+        cur = nxt;
     }
     if (partials) {
         const int slots[3] = {S_TVY, S_BRY, S_XY2};
