@@ -34,6 +34,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
+
+# HBM bytes per launch of the stored-A^T product, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE scaled by a 1 GiB copy (profiles/cone256_kernels_hbm_traffic_pmc.md);
+# reported only while the kernel source is the one measured.
+MEASURED_TRAFFIC = {"kernel": "backproject", "source": "paper_1105_4002_amd/csrc/matrix.hip",
+                    "sha256_prefix": "1fac8cd6fbb0b308", "bytes": 12.27e9 + 0.067e9}
+
+
+def measured_traffic(kernel: str, stored: bool):
+    import hashlib
+    if not stored or kernel != MEASURED_TRAFFIC["kernel"]:
+        return None
+    with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"]), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if not sha.startswith(MEASURED_TRAFFIC["sha256_prefix"]):
+        return None
+    return round(MEASURED_TRAFFIC["bytes"] / 1e9, 3)
 FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed math)
 
 
@@ -240,7 +257,10 @@ def main() -> int:
     scale = 1e12 if unit == "TFLOP/s" else 1e9
     roofline = {"kernel": dom, "bound": bound, "achieved": round(amount / avg_s / scale, 3),
                 "peak": peak / scale, "unit": unit, "frac": round(amount / avg_s / peak, 4),
-                "traffic": None}
+                "traffic": measured_traffic(dom, stored)}
+    if roofline["traffic"] is not None:
+        roofline["traffic_unit"] = "GB per launch"
+        roofline["algorithmic"] = round(amount / 1e9, 3)
 
     result = {
         "metric": "gradient evals/sec + time to 1e-6 gradient-map tol, 256^3 UPN FP32 vs FP64",
