@@ -124,6 +124,37 @@ tvreg_status tvreg_matrix_attach(tvreg_geometry *geom, void *matrix_dev, size_t 
                                  void *stream);
 tvreg_status tvreg_matrix_detach(tvreg_geometry *geom);
 
+/*
+ * Tile shapes of the on-the-fly operators (a performance choice only: every
+ * shape gives bitwise identical projections and backprojections; the block
+ * partial sums of the projector's fused residual norm, and so the last bits
+ * of the solver's FP64 sums, follow the shape).
+ *   project_rows       detector rows per projector block of 64 columns:
+ *                      1, 2, 4 (default) or 8;
+ *   backproject_depth  voxels per thread along z in the on-the-fly
+ *                      backprojector: 4, 8 (default) or 16.
+ * tvreg_autotune times every shape on the geometry (zero-filled synthetic
+ * operands in `ws_dev`, `reps` launches per shape after one warm-up, HIP
+ * events on `stream`), keeps the fastest of each operator in the geometry
+ * and reports all timings; it synchronises `stream` and must not run while
+ * another call uses the geometry.  The backprojector is timed on the fly
+ * even when a stored transpose is attached.  tvreg_solve_batched always
+ * uses the default shapes.
+ */
+typedef struct {
+    int32_t project_rows;
+    int32_t backproject_depth;
+    double project_ms[4];      /* tvreg_autotune: ms per projection for 1, 2, 4, 8 rows */
+    double backproject_ms[3];  /* tvreg_autotune: ms per backprojection for depth 4, 8, 16 */
+} tvreg_tuning;
+size_t tvreg_autotune_workspace_bytes(const tvreg_geometry *geom);
+tvreg_status tvreg_autotune(tvreg_geometry *geom, void *ws_dev, size_t ws_bytes, int32_t reps,
+                            tvreg_tuning *out, void *stream);
+/* the geometry's current shapes (timings zero) */
+tvreg_status tvreg_get_tuning(const tvreg_geometry *geom, tvreg_tuning *out);
+/* sets both shapes; EINVAL for a value outside the lists above */
+tvreg_status tvreg_set_tuning(tvreg_geometry *geom, const tvreg_tuning *tuning);
+
 /* Bytes of device workspace tvreg_tv_grad and tvreg_objective_grad need. */
 size_t tvreg_tv_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
 

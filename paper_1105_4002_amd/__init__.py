@@ -47,6 +47,15 @@ class _SolveParams(ctypes.Structure):
                 ("hist_len", ctypes.c_int32)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("project_rows", ctypes.c_int32), ("backproject_depth", ctypes.c_int32),
+                ("project_ms", ctypes.c_double * 4), ("backproject_ms", ctypes.c_double * 3)]
+
+
+PROJECT_ROWS = (1, 2, 4, 8)
+BACKPROJECT_DEPTHS = (4, 8, 16)
+
+
 class _SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("grad_evals", ctypes.c_int32),
                 ("func_evals", ctypes.c_int32), ("phi", ctypes.c_double),
@@ -58,7 +67,8 @@ class _SolveInfo(ctypes.Structure):
 # Every symbol include/tvreg.h declares.
 EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
            "tvreg_backproject", "tvreg_matrix_scratch_bytes", "tvreg_matrix_plan",
-           "tvreg_matrix_attach", "tvreg_matrix_detach", "tvreg_tv_workspace_bytes",
+           "tvreg_matrix_attach", "tvreg_matrix_detach", "tvreg_autotune_workspace_bytes",
+           "tvreg_autotune", "tvreg_get_tuning", "tvreg_set_tuning", "tvreg_tv_workspace_bytes",
            "tvreg_tv_grad", "tvreg_tv_hessvec",
            "tvreg_objective_workspace_bytes", "tvreg_objective_grad",
            "tvreg_solve_workspace_bytes", "tvreg_solve", "tvreg_solve_batched_workspace_bytes",
@@ -94,6 +104,14 @@ def _load():
     L.tvreg_matrix_attach.restype = st
     L.tvreg_matrix_detach.argtypes = [vp]
     L.tvreg_matrix_detach.restype = st
+    L.tvreg_autotune_workspace_bytes.argtypes = [vp]
+    L.tvreg_autotune_workspace_bytes.restype = sz
+    L.tvreg_autotune.argtypes = [vp, vp, sz, ctypes.c_int32, ctypes.POINTER(_Tuning), vp]
+    L.tvreg_autotune.restype = st
+    L.tvreg_get_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+    L.tvreg_get_tuning.restype = st
+    L.tvreg_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+    L.tvreg_set_tuning.restype = st
     L.tvreg_tv_workspace_bytes.argtypes = [ctypes.c_int32] * 3
     L.tvreg_tv_workspace_bytes.restype = sz
     L.tvreg_tv_grad.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int, ctypes.c_double, vp, vp,
@@ -232,6 +250,30 @@ class Geometry:
     def matrix_bytes(self) -> int:
         m = getattr(self, "_matrix", None)
         return 0 if m is None else m.numel()
+
+    def autotune(self, reps: int = 5, device="cuda") -> dict:
+        """Times every tile shape of the on-the-fly projector and
+        backprojector on this geometry (tvreg_autotune), keeps the fastest and
+        returns the choice with all timings (ms per launch)."""
+        ws = torch.empty(_lib.tvreg_autotune_workspace_bytes(self.handle), dtype=torch.uint8,
+                         device=device)
+        t = _Tuning()
+        _check(_lib.tvreg_autotune(self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   int(reps), ctypes.byref(t), _stream(ws)), "tvreg_autotune")
+        return {"project_rows": t.project_rows, "backproject_depth": t.backproject_depth,
+                "project_ms": dict(zip(PROJECT_ROWS, list(t.project_ms))),
+                "backproject_ms": dict(zip(BACKPROJECT_DEPTHS, list(t.backproject_ms)))}
+
+    @property
+    def tuning(self) -> tuple:
+        """(project_rows, backproject_depth) currently used."""
+        t = _Tuning()
+        _check(_lib.tvreg_get_tuning(self.handle, ctypes.byref(t)), "tvreg_get_tuning")
+        return (t.project_rows, t.backproject_depth)
+
+    def set_tuning(self, project_rows: int, backproject_depth: int) -> None:
+        t = _Tuning(int(project_rows), int(backproject_depth))
+        _check(_lib.tvreg_set_tuning(self.handle, ctypes.byref(t)), "tvreg_set_tuning")
 
     def empty_volume(self, device="cuda"):
         return torch.empty(self.vol_shape, dtype=self.dtype, device=device)

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build", "tvreg")
 LIB_PATH = os.path.join(PKG, "libtvreg.so")
 SOURCES = ["project.hip", "backproject.hip", "matrix.hip", "stencil.hip", "adjoint.hip", "batch.hip",
-           "unrolled.hip", "api.hip"]
+           "unrolled.hip", "tune.hip", "api.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

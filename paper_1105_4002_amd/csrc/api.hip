@@ -208,7 +208,11 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     g.col = (const ColEntry *)(base + o_col);
     g.row = (const RowEntry *)(base + o_row);
     g.dnorm = (const double *)(base + o_dn);
-    G->pstride = std::max({project_blocks(g), max_reduce_blocks_vol(g.nx, g.ny, g.nz),
+    g.mat = MatDev{};
+    g.pj_ty = PJ_TY_DEFAULT;
+    g.bp_cz = BP_CZ_DEFAULT;
+    // partial sums sized for every projector tile shape the tuner may pick
+    G->pstride = std::max({project_blocks_max(g), max_reduce_blocks_vol(g.nx, g.ny, g.nz),
                            elementwise_blocks(N), elementwise_blocks(m)});
     *out = G;
     return TVREG_OK;

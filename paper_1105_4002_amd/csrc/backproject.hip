@@ -30,7 +30,6 @@ namespace {
 constexpr int BP_TX = 16;   // voxel columns per block along x
 constexpr int BP_TY = 16;   // ... along y
 constexpr int BP_THREADS = BP_TX * BP_TY;
-constexpr int BP_CZ = 8;    // voxels per thread along z
 constexpr int TILE_C = 48;  // detector columns a block stages per view
 constexpr int TILE_R = 32;  // detector rows a block stages per view
 constexpr int TILE_S = TILE_C + 1;  // odd row stride (in doubles) against bank conflicts
@@ -242,6 +241,7 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_grouped(BatchProblem<T
     if (P.state != B_RUNNING || !P.need_grad)
         return;
     const int local = blockIdx.x - offs[p];
+    constexpr int BP_CZ = BP_CZ_DEFAULT;
     const int gx = (P.g.nx + BP_TX - 1) / BP_TX, gy = (P.g.ny + BP_TY - 1) / BP_TY;
     const int bx = local % gx, by = (local / gx) % gy, bz = local / (gx * gy);
     if (P.g.cone)
@@ -252,10 +252,11 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_grouped(BatchProblem<T
 
 }  // namespace
 
+// blocks of the grouped (default-shape) backprojector
 int backproject_blocks(const GeomDev &g)
 {
     return ((g.nx + BP_TX - 1) / BP_TX) * ((g.ny + BP_TY - 1) / BP_TY) *
-           ((g.nz + BP_CZ - 1) / BP_CZ);
+           ((g.nz + BP_CZ_DEFAULT - 1) / BP_CZ_DEFAULT);
 }
 
 template <typename T>
@@ -272,18 +273,33 @@ template hipError_t launch_backproject_grouped<float>(BatchProblem<float> *, con
 template hipError_t launch_backproject_grouped<double>(BatchProblem<double> *, const int *, int,
                                                        int, hipStream_t);
 
+template <typename T, int CZ>
+static void launch_backproject_cz(const GeomDev &g, const T *r, T *out, hipStream_t st)
+{
+    dim3 block(BP_THREADS, 1, 1);
+    dim3 grid((g.nx + BP_TX - 1) / BP_TX, (g.ny + BP_TY - 1) / BP_TY, (g.nz + CZ - 1) / CZ);
+    if (g.cone)
+        hipLaunchKernelGGL((backproject_kernel<T, true, CZ>), grid, block, 0, st, g, r, out);
+    else
+        hipLaunchKernelGGL((backproject_kernel<T, false, CZ>), grid, block, 0, st, g, r, out);
+}
+
 template <typename T>
 hipError_t launch_backproject(const GeomDev &g, const T *r, T *out, hipStream_t st)
 {
     if (g.mat.present)
         return launch_backproject_matrix<T>(g, r, out, st);
-    dim3 block(BP_THREADS, 1, 1);
-    dim3 grid((g.nx + BP_TX - 1) / BP_TX, (g.ny + BP_TY - 1) / BP_TY,
-              (g.nz + BP_CZ - 1) / BP_CZ);
-    if (g.cone)
-        hipLaunchKernelGGL((backproject_kernel<T, true, BP_CZ>), grid, block, 0, st, g, r, out);
-    else
-        hipLaunchKernelGGL((backproject_kernel<T, false, BP_CZ>), grid, block, 0, st, g, r, out);
+    switch (g.bp_cz) {
+    case 4:
+        launch_backproject_cz<T, 4>(g, r, out, st);
+        break;
+    case 16:
+        launch_backproject_cz<T, 16>(g, r, out, st);
+        break;
+    default:
+        launch_backproject_cz<T, 8>(g, r, out, st);
+        break;
+    }
     return hipGetLastError();
 }
 

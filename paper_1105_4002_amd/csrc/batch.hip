@@ -195,9 +195,19 @@ size_t batch_bytes(int n, const tvreg_geometry *const *geoms, std::vector<size_t
     return off;
 }
 
+// grouped launches use the default tile shapes whatever the geometry's tuning
+GeomDev default_shapes(const GeomDev &g0)
+{
+    GeomDev g = g0;
+    g.mat = MatDev{};  // and evaluate the operators on the fly
+    g.pj_ty = PJ_TY_DEFAULT;
+    g.bp_cz = BP_CZ_DEFAULT;
+    return g;
+}
+
 int family_blocks(const tvreg_geometry *G, int f)
 {
-    const GeomDev &g = G->g;
+    const GeomDev g = default_shapes(G->g);
     switch (f) {
     case F_BP:
         return backproject_blocks(g);
@@ -252,12 +262,11 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         char *r = ws + base[i];
         BatchProblem<T> &P = hp[i];
         memset(&P, 0, sizeof(P));
-        P.g = G->g;
-        P.g.mat = MatDev{};  // grouped launches evaluate the operators on the fly
+        P.g = default_shapes(G->g);
         P.N = (int)G->N;
         P.m = (int)G->m;
         P.nb_vox = max_reduce_blocks_vol(G->g.nx, G->g.ny, G->g.nz);
-        P.nb_proj = project_blocks(G->g);
+        P.nb_proj = project_blocks(P.g);
         P.nb_ew = elementwise_blocks(G->m);
         P.pstride = G->pstride;
         P.X = (T *)(r + vN[0]);

@@ -20,10 +20,9 @@ namespace tvr {
 namespace {
 
 constexpr int PJ_TX = 64;  // detector columns per block (one wavefront)
-constexpr int PJ_TY = 4;   // detector rows per block
 
-// One block: PJ_TX detector columns x PJ_TY rows of view v.
-template <typename T, bool CONE>
+// One block: PJ_TX detector columns x TY rows of view v.
+template <typename T, bool CONE, int TY>
 __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restrict__ x,
                                               const T *__restrict__ xt, const T *__restrict__ b,
                                               T *__restrict__ out, const T *__restrict__ rref,
@@ -31,7 +30,7 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
                                               int bx, int by, int v, int bid)
 {
     const int col = bx * PJ_TX + threadIdx.x;
-    const int row = by * PJ_TY + threadIdx.y;
+    const int row = by * TY + threadIdx.y;
     double red[2] = {0.0, 0.0};
     if (col < g.cols && row < g.rows) {
         const ColEntry ce = g.col[(size_t)v * g.cols + col];
@@ -59,8 +58,8 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
     }
 }
 
-template <typename T, bool CONE>
-__global__ __launch_bounds__(PJ_TX *PJ_TY) void project_kernel(GeomDev g, const T *__restrict__ x,
+template <typename T, bool CONE, int TY>
+__global__ __launch_bounds__(PJ_TX *TY) void project_kernel(GeomDev g, const T *__restrict__ x,
                                                               const T *__restrict__ xt,
                                                               const T *__restrict__ b,
                                                               T *__restrict__ out,
@@ -68,14 +67,14 @@ __global__ __launch_bounds__(PJ_TX *PJ_TY) void project_kernel(GeomDev g, const 
                                                               double *__restrict__ partials,
                                                               int pstride)
 {
-    project_block<T, CONE>(g, x, xt, b, out, rref, partials, pstride, blockIdx.x, blockIdx.y,
-                           blockIdx.z, block_linear_id());
+    project_block<T, CONE, TY>(g, x, xt, b, out, rref, partials, pstride, blockIdx.x, blockIdx.y,
+                               blockIdx.z, block_linear_id());
 }
 
 // Batched: the trial points XB of every running problem (residual against
 // b, Bregman data term against RY).
 template <typename T>
-__global__ __launch_bounds__(PJ_TX *PJ_TY) void project_grouped(BatchProblem<T> *probs,
+__global__ __launch_bounds__(PJ_TX *PJ_TY_DEFAULT) void project_grouped(BatchProblem<T> *probs,
                                                                const int *offs, int n)
 {
     const int p = find_problem(offs, n, blockIdx.x);
@@ -83,14 +82,15 @@ __global__ __launch_bounds__(PJ_TX *PJ_TY) void project_grouped(BatchProblem<T> 
     if (P.state != B_RUNNING)
         return;
     const int local = blockIdx.x - offs[p];
-    const int gx = (P.g.cols + PJ_TX - 1) / PJ_TX, gy = (P.g.rows + PJ_TY - 1) / PJ_TY;
+    constexpr int TY = PJ_TY_DEFAULT;
+    const int gx = (P.g.cols + PJ_TX - 1) / PJ_TX, gy = (P.g.rows + TY - 1) / TY;
     const int bx = local % gx, by = (local / gx) % gy, v = local / (gx * gy);
     if (P.g.cone)
-        project_block<T, true>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx, by, v,
-                               local);
+        project_block<T, true, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx, by,
+                                   v, local);
     else
-        project_block<T, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx, by, v,
-                                local);
+        project_block<T, false, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx, by,
+                                    v, local);
 }
 
 }  // namespace
@@ -99,8 +99,8 @@ template <typename T>
 hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                                   hipStream_t st)
 {
-    hipLaunchKernelGGL((project_grouped<T>), dim3(blocks), dim3(PJ_TX, PJ_TY), 0, st, probs,
-                       offs, n);
+    hipLaunchKernelGGL((project_grouped<T>), dim3(blocks), dim3(PJ_TX, PJ_TY_DEFAULT), 0, st,
+                       probs, offs, n);
     return hipGetLastError();
 }
 
@@ -109,27 +109,53 @@ template hipError_t launch_project_grouped<float>(BatchProblem<float> *, const i
 template hipError_t launch_project_grouped<double>(BatchProblem<double> *, const int *, int, int,
                                                    hipStream_t);
 
+template <typename T, int TY>
+static void launch_project_ty(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,
+                              const T *rref, double *partials, int pstride, hipStream_t st)
+{
+    dim3 block(PJ_TX, TY, 1);
+    dim3 grid((g.cols + PJ_TX - 1) / PJ_TX, (g.rows + TY - 1) / TY, g.nviews);
+    if (g.cone)
+        hipLaunchKernelGGL((project_kernel<T, true, TY>), grid, block, 0, st, g, x, xt, b, out,
+                           rref, partials, pstride);
+    else
+        hipLaunchKernelGGL((project_kernel<T, false, TY>), grid, block, 0, st, g, x, xt, b, out,
+                           rref, partials, pstride);
+}
+
 template <typename T>
 hipError_t launch_project(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,
                           const T *rref, double *partials, int pstride, hipStream_t st,
                           int *nblocks)
 {
-    dim3 block(PJ_TX, PJ_TY, 1);
-    dim3 grid((g.cols + PJ_TX - 1) / PJ_TX, (g.rows + PJ_TY - 1) / PJ_TY, g.nviews);
     if (nblocks)
-        *nblocks = (int)(grid.x * grid.y * grid.z);
-    if (g.cone)
-        hipLaunchKernelGGL((project_kernel<T, true>), grid, block, 0, st, g, x, xt, b, out,
-                           rref, partials, pstride);
-    else
-        hipLaunchKernelGGL((project_kernel<T, false>), grid, block, 0, st, g, x, xt, b, out,
-                           rref, partials, pstride);
+        *nblocks = project_blocks(g);
+    switch (g.pj_ty) {
+    case 1:
+        launch_project_ty<T, 1>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    case 2:
+        launch_project_ty<T, 2>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    case 8:
+        launch_project_ty<T, 8>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    default:
+        launch_project_ty<T, 4>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    }
     return hipGetLastError();
 }
 
 int project_blocks(const GeomDev &g)
 {
-    return ((g.cols + PJ_TX - 1) / PJ_TX) * ((g.rows + PJ_TY - 1) / PJ_TY) * g.nviews;
+    const int ty = g.pj_ty == 1 || g.pj_ty == 2 || g.pj_ty == 8 ? g.pj_ty : 4;
+    return ((g.cols + PJ_TX - 1) / PJ_TX) * ((g.rows + ty - 1) / ty) * g.nviews;
+}
+
+int project_blocks_max(const GeomDev &g)
+{
+    return ((g.cols + PJ_TX - 1) / PJ_TX) * g.rows * g.nviews;  // one row per block
 }
 
 template hipError_t launch_project<float>(const GeomDev &, const float *, const float *,

@@ -54,7 +54,13 @@ struct GeomDev {
     const RowEntry *row;       // [rows]
     const double *dnorm;       // |D|: cone [rows * cols], parallel [nviews]
     MatDev mat;                // stored A^T when present
+    int pj_ty;                 // projector: detector rows per block of 64 columns (1, 2, 4, 8)
+    int bp_cz;                 // on-the-fly backprojector: voxels per thread along z (4, 8, 16)
 };
+
+// default tile shapes (the batched solve always uses these)
+constexpr int PJ_TY_DEFAULT = 4;
+constexpr int BP_CZ_DEFAULT = 8;
 
 // Double-precision reduction results live in fixed slots; every kernel that
 // reduces writes one partial per block into partials[slot * pstride + block]
@@ -170,8 +176,10 @@ hipError_t launch_adj_extrap(int64_t n, double beta, const T *ybar, const T *xn,
                              T *xbar_n, T *xbar_o, double *partials, int pstride, hipStream_t st,
                              int *nblocks);
 
-// grid limits used to size the partial-sum buffer
+// grid limits used to size the partial-sum buffer (for the geometry's tile
+// shapes; project_blocks_max: the largest over the projector's shapes)
 int project_blocks(const GeomDev &g);
+int project_blocks_max(const GeomDev &g);
 int max_reduce_blocks_vol(int nx, int ny, int nz);
 int elementwise_blocks(int64_t n);
 int backproject_blocks(const GeomDev &g);
