@@ -129,8 +129,11 @@ tvreg_status tvreg_matrix_detach(tvreg_geometry *geom);
  * shape gives bitwise identical projections and backprojections; the block
  * partial sums of the projector's fused residual norm, and so the last bits
  * of the solver's FP64 sums, follow the shape).
- *   project_rows       detector rows per projector block of 64 columns:
- *                      1, 2, 4 (default) or 8;
+ *   project_tile_cols  detector columns of the ray tile one wavefront walks;
+ *                      the tile is project_tile_cols x (64 / project_tile_cols)
+ *                      pixels: 8, 16, 32 or 64 (default);
+ *   project_waves      ray tiles per projector block, stacked along the
+ *                      detector rows: 1, 2, 4 (default) or 8;
  *   backproject_depth  voxels per thread along z in the on-the-fly
  *                      backprojector: 4, 8 (default) or 16.
  * tvreg_autotune times every shape on the geometry (zero-filled synthetic
@@ -142,10 +145,13 @@ tvreg_status tvreg_matrix_detach(tvreg_geometry *geom);
  * uses the default shapes.
  */
 typedef struct {
-    int32_t project_rows;
+    int32_t project_tile_cols;
+    int32_t project_waves;
     int32_t backproject_depth;
-    double project_ms[4];      /* tvreg_autotune: ms per projection for 1, 2, 4, 8 rows */
-    double backproject_ms[3];  /* tvreg_autotune: ms per backprojection for depth 4, 8, 16 */
+    int32_t reserved;            /* 0 */
+    double project_ms[4][4];     /* tvreg_autotune: ms per projection, [tile cols 8, 16, 32, 64]
+                                    [waves 1, 2, 4, 8] */
+    double backproject_ms[3];    /* tvreg_autotune: ms per backprojection for depth 4, 8, 16 */
 } tvreg_tuning;
 size_t tvreg_autotune_workspace_bytes(const tvreg_geometry *geom);
 tvreg_status tvreg_autotune(tvreg_geometry *geom, void *ws_dev, size_t ws_bytes, int32_t reps,

@@ -48,11 +48,14 @@ class _SolveParams(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("project_rows", ctypes.c_int32), ("backproject_depth", ctypes.c_int32),
-                ("project_ms", ctypes.c_double * 4), ("backproject_ms", ctypes.c_double * 3)]
+    _fields_ = [("project_tile_cols", ctypes.c_int32), ("project_waves", ctypes.c_int32),
+                ("backproject_depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("project_ms", (ctypes.c_double * 4) * 4),
+                ("backproject_ms", ctypes.c_double * 3)]
 
 
-PROJECT_ROWS = (1, 2, 4, 8)
+PROJECT_TILE_COLS = (8, 16, 32, 64)
+PROJECT_WAVES = (1, 2, 4, 8)
 BACKPROJECT_DEPTHS = (4, 8, 16)
 
 
@@ -260,19 +263,23 @@ class Geometry:
         t = _Tuning()
         _check(_lib.tvreg_autotune(self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                    int(reps), ctypes.byref(t), _stream(ws)), "tvreg_autotune")
-        return {"project_rows": t.project_rows, "backproject_depth": t.backproject_depth,
-                "project_ms": dict(zip(PROJECT_ROWS, list(t.project_ms))),
+        return {"project_tile_cols": t.project_tile_cols, "project_waves": t.project_waves,
+                "backproject_depth": t.backproject_depth,
+                "project_ms": {(c, w): t.project_ms[a][i]
+                               for a, c in enumerate(PROJECT_TILE_COLS)
+                               for i, w in enumerate(PROJECT_WAVES)},
                 "backproject_ms": dict(zip(BACKPROJECT_DEPTHS, list(t.backproject_ms)))}
 
     @property
     def tuning(self) -> tuple:
-        """(project_rows, backproject_depth) currently used."""
+        """(project_tile_cols, project_waves, backproject_depth) currently used."""
         t = _Tuning()
         _check(_lib.tvreg_get_tuning(self.handle, ctypes.byref(t)), "tvreg_get_tuning")
-        return (t.project_rows, t.backproject_depth)
+        return (t.project_tile_cols, t.project_waves, t.backproject_depth)
 
-    def set_tuning(self, project_rows: int, backproject_depth: int) -> None:
-        t = _Tuning(int(project_rows), int(backproject_depth))
+    def set_tuning(self, project_tile_cols: int, project_waves: int,
+                   backproject_depth: int) -> None:
+        t = _Tuning(int(project_tile_cols), int(project_waves), int(backproject_depth), 0)
         _check(_lib.tvreg_set_tuning(self.handle, ctypes.byref(t)), "tvreg_set_tuning")
 
     def empty_volume(self, device="cuda"):

@@ -209,6 +209,7 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     g.row = (const RowEntry *)(base + o_row);
     g.dnorm = (const double *)(base + o_dn);
     g.mat = MatDev{};
+    g.pj_wc = PJ_WC_DEFAULT;
     g.pj_ty = PJ_TY_DEFAULT;
     g.bp_cz = BP_CZ_DEFAULT;
     // partial sums sized for every projector tile shape the tuner may pick

@@ -200,6 +200,7 @@ GeomDev default_shapes(const GeomDev &g0)
 {
     GeomDev g = g0;
     g.mat = MatDev{};  // and evaluate the operators on the fly
+    g.pj_wc = PJ_WC_DEFAULT;
     g.pj_ty = PJ_TY_DEFAULT;
     g.bp_cz = BP_CZ_DEFAULT;
     return g;

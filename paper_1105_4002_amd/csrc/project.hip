@@ -11,6 +11,8 @@
 // r = A x - b, and the block writes FP64 partial sums of r_i^2 and, with
 // rref, of (r_i - rref_i)^2 (the data part of the Bregman distance used by
 // the line search).
+#include <algorithm>
+
 #include "raywalk.hpp"
 #include "reduce.hpp"
 #include "tvreg_internal.hpp"
@@ -19,18 +21,27 @@ namespace tvr {
 
 namespace {
 
-constexpr int PJ_TX = 64;  // detector columns per block (one wavefront)
+// Ray tiles.  A wavefront of 64 threads walks the rays of a WC x (64 / WC)
+// patch of detector pixels (columns x rows); a block stacks TY such patches
+// along the rows.  Neighbouring rays have similar lengths through the
+// volume, so a square patch keeps more lanes busy until the wave's longest
+// ray ends than a 64 x 1 strip does (in a cone beam, the strip mixes rays
+// through the middle of the volume with rays that only clip an edge).
+template <int WC>
+struct RayTile {
+    static constexpr int rows = 64 / WC;  // detector rows per wave
+};
 
-// One block: PJ_TX detector columns x TY rows of view v.
-template <typename T, bool CONE, int TY>
+// One block: WC detector columns x (TY * 64 / WC) rows of view v.
+template <typename T, bool CONE, int WC, int TY>
 __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restrict__ x,
                                               const T *__restrict__ xt, const T *__restrict__ b,
                                               T *__restrict__ out, const T *__restrict__ rref,
                                               double *__restrict__ partials, int pstride,
                                               int bx, int by, int v, int bid)
 {
-    const int col = bx * PJ_TX + threadIdx.x;
-    const int row = by * TY + threadIdx.y;
+    const int col = bx * WC + (int)threadIdx.x % WC;
+    const int row = (by * TY + (int)threadIdx.y) * RayTile<WC>::rows + (int)threadIdx.x / WC;
     double red[2] = {0.0, 0.0};
     if (col < g.cols && row < g.rows) {
         const ColEntry ce = g.col[(size_t)v * g.cols + col];
@@ -58,8 +69,8 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
     }
 }
 
-template <typename T, bool CONE, int TY>
-__global__ __launch_bounds__(PJ_TX *TY) void project_kernel(GeomDev g, const T *__restrict__ x,
+template <typename T, bool CONE, int WC, int TY>
+__global__ __launch_bounds__(64 * TY) void project_kernel(GeomDev g, const T *__restrict__ x,
                                                               const T *__restrict__ xt,
                                                               const T *__restrict__ b,
                                                               T *__restrict__ out,
@@ -67,14 +78,14 @@ __global__ __launch_bounds__(PJ_TX *TY) void project_kernel(GeomDev g, const T *
                                                               double *__restrict__ partials,
                                                               int pstride)
 {
-    project_block<T, CONE, TY>(g, x, xt, b, out, rref, partials, pstride, blockIdx.x, blockIdx.y,
-                               blockIdx.z, block_linear_id());
+    project_block<T, CONE, WC, TY>(g, x, xt, b, out, rref, partials, pstride, blockIdx.x,
+                                   blockIdx.y, blockIdx.z, block_linear_id());
 }
 
 // Batched: the trial points XB of every running problem (residual against
 // b, Bregman data term against RY).
 template <typename T>
-__global__ __launch_bounds__(PJ_TX *PJ_TY_DEFAULT) void project_grouped(BatchProblem<T> *probs,
+__global__ __launch_bounds__(64 * PJ_TY_DEFAULT) void project_grouped(BatchProblem<T> *probs,
                                                                const int *offs, int n)
 {
     const int p = find_problem(offs, n, blockIdx.x);
@@ -82,15 +93,15 @@ __global__ __launch_bounds__(PJ_TX *PJ_TY_DEFAULT) void project_grouped(BatchPro
     if (P.state != B_RUNNING)
         return;
     const int local = blockIdx.x - offs[p];
-    constexpr int TY = PJ_TY_DEFAULT;
-    const int gx = (P.g.cols + PJ_TX - 1) / PJ_TX, gy = (P.g.rows + TY - 1) / TY;
+    constexpr int WC = PJ_WC_DEFAULT, TY = PJ_TY_DEFAULT, BR = TY * RayTile<WC>::rows;
+    const int gx = (P.g.cols + WC - 1) / WC, gy = (P.g.rows + BR - 1) / BR;
     const int bx = local % gx, by = (local / gx) % gy, v = local / (gx * gy);
     if (P.g.cone)
-        project_block<T, true, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx, by,
-                                   v, local);
+        project_block<T, true, WC, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx,
+                                       by, v, local);
     else
-        project_block<T, false, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx, by,
-                                    v, local);
+        project_block<T, false, WC, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx,
+                                        by, v, local);
 }
 
 }  // namespace
@@ -99,8 +110,8 @@ template <typename T>
 hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                                   hipStream_t st)
 {
-    hipLaunchKernelGGL((project_grouped<T>), dim3(blocks), dim3(PJ_TX, PJ_TY_DEFAULT), 0, st,
-                       probs, offs, n);
+    hipLaunchKernelGGL((project_grouped<T>), dim3(blocks), dim3(64, PJ_TY_DEFAULT), 0, st, probs,
+                       offs, n);
     return hipGetLastError();
 }
 
@@ -109,19 +120,53 @@ template hipError_t launch_project_grouped<float>(BatchProblem<float> *, const i
 template hipError_t launch_project_grouped<double>(BatchProblem<double> *, const int *, int, int,
                                                    hipStream_t);
 
-template <typename T, int TY>
-static void launch_project_ty(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,
-                              const T *rref, double *partials, int pstride, hipStream_t st)
+namespace {
+
+int grid_blocks(const GeomDev &g, int wc, int ty)
 {
-    dim3 block(PJ_TX, TY, 1);
-    dim3 grid((g.cols + PJ_TX - 1) / PJ_TX, (g.rows + TY - 1) / TY, g.nviews);
-    if (g.cone)
-        hipLaunchKernelGGL((project_kernel<T, true, TY>), grid, block, 0, st, g, x, xt, b, out,
-                           rref, partials, pstride);
-    else
-        hipLaunchKernelGGL((project_kernel<T, false, TY>), grid, block, 0, st, g, x, xt, b, out,
-                           rref, partials, pstride);
+    const int br = ty * (64 / wc);
+    return ((g.cols + wc - 1) / wc) * ((g.rows + br - 1) / br) * g.nviews;
 }
+
+template <typename T, int WC, int TY>
+void launch_shape(const GeomDev &g, const T *x, const T *xt, const T *b, T *out, const T *rref,
+                  double *partials, int pstride, hipStream_t st)
+{
+    constexpr int BR = TY * RayTile<WC>::rows;
+    dim3 block(64, TY, 1);
+    dim3 grid((g.cols + WC - 1) / WC, (g.rows + BR - 1) / BR, g.nviews);
+    if (g.cone)
+        hipLaunchKernelGGL((project_kernel<T, true, WC, TY>), grid, block, 0, st, g, x, xt, b,
+                           out, rref, partials, pstride);
+    else
+        hipLaunchKernelGGL((project_kernel<T, false, WC, TY>), grid, block, 0, st, g, x, xt, b,
+                           out, rref, partials, pstride);
+}
+
+template <typename T, int WC>
+void launch_wc(const GeomDev &g, const T *x, const T *xt, const T *b, T *out, const T *rref,
+               double *partials, int pstride, hipStream_t st)
+{
+    switch (g.pj_ty) {
+    case 1:
+        launch_shape<T, WC, 1>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    case 2:
+        launch_shape<T, WC, 2>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    case 8:
+        launch_shape<T, WC, 8>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    default:
+        launch_shape<T, WC, 4>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    }
+}
+
+int valid_ty(int ty) { return ty == 1 || ty == 2 || ty == 8 ? ty : 4; }
+int valid_wc(int wc) { return wc == 8 || wc == 16 || wc == 32 ? wc : 64; }
+
+}  // namespace
 
 template <typename T>
 hipError_t launch_project(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,
@@ -130,32 +175,31 @@ hipError_t launch_project(const GeomDev &g, const T *x, const T *xt, const T *b,
 {
     if (nblocks)
         *nblocks = project_blocks(g);
-    switch (g.pj_ty) {
-    case 1:
-        launch_project_ty<T, 1>(g, x, xt, b, out, rref, partials, pstride, st);
-        break;
-    case 2:
-        launch_project_ty<T, 2>(g, x, xt, b, out, rref, partials, pstride, st);
-        break;
+    switch (valid_wc(g.pj_wc)) {
     case 8:
-        launch_project_ty<T, 8>(g, x, xt, b, out, rref, partials, pstride, st);
+        launch_wc<T, 8>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    case 16:
+        launch_wc<T, 16>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    case 32:
+        launch_wc<T, 32>(g, x, xt, b, out, rref, partials, pstride, st);
         break;
     default:
-        launch_project_ty<T, 4>(g, x, xt, b, out, rref, partials, pstride, st);
+        launch_wc<T, 64>(g, x, xt, b, out, rref, partials, pstride, st);
         break;
     }
     return hipGetLastError();
 }
 
-int project_blocks(const GeomDev &g)
-{
-    const int ty = g.pj_ty == 1 || g.pj_ty == 2 || g.pj_ty == 8 ? g.pj_ty : 4;
-    return ((g.cols + PJ_TX - 1) / PJ_TX) * ((g.rows + ty - 1) / ty) * g.nviews;
-}
+int project_blocks(const GeomDev &g) { return grid_blocks(g, valid_wc(g.pj_wc), valid_ty(g.pj_ty)); }
 
 int project_blocks_max(const GeomDev &g)
 {
-    return ((g.cols + PJ_TX - 1) / PJ_TX) * g.rows * g.nviews;  // one row per block
+    int mx = 0;
+    for (int wc = 8; wc <= 64; wc *= 2)  // one wave per block gives the most blocks
+        mx = std::max(mx, grid_blocks(g, wc, 1));
+    return mx;
 }
 
 template hipError_t launch_project<float>(const GeomDev &, const float *, const float *,

@@ -1,5 +1,5 @@
-// Autotuner of the on-the-fly operators' tile shapes: the projector's
-// detector rows per block of 64 columns and the gather backprojector's
+// Autotuner of the on-the-fly operators' tile shapes: the projector's ray
+// tile per wavefront and waves per block, and the gather backprojector's
 // voxels per thread along z.  Both operators visit the same rays and voxels
 // in the same per-output order whatever the shape (a thread owns a ray, or
 // a voxel column chunk), so the choice changes speed only; their control
@@ -14,10 +14,12 @@ using namespace tvr;
 
 namespace {
 
+constexpr int WC_SHAPES[4] = {8, 16, 32, 64};
 constexpr int PJ_SHAPES[4] = {1, 2, 4, 8};
 constexpr int BP_SHAPES[3] = {4, 8, 16};
 
-bool valid_rows(int v) { return std::find(PJ_SHAPES, PJ_SHAPES + 4, v) != PJ_SHAPES + 4; }
+bool valid_cols(int v) { return std::find(WC_SHAPES, WC_SHAPES + 4, v) != WC_SHAPES + 4; }
+bool valid_waves(int v) { return std::find(PJ_SHAPES, PJ_SHAPES + 4, v) != PJ_SHAPES + 4; }
 bool valid_depth(int v) { return std::find(BP_SHAPES, BP_SHAPES + 3, v) != BP_SHAPES + 3; }
 
 struct Events {
@@ -67,17 +69,23 @@ tvreg_status tune_impl(tvreg_geometry *G, char *ws, int reps, tvreg_tuning *out,
     g.mat = MatDev{};
     tvreg_tuning t{};
     double best = INFINITY;
-    t.project_rows = G->g.pj_ty;
-    for (int i = 0; i < 4; ++i) {
-        g.pj_ty = PJ_SHAPES[i];
-        TVR_TRY(time_launches(
-            [&] {
-                return launch_project<T>(g, x, xt, b, y, nullptr, part, G->pstride, st, nullptr);
-            },
-            reps, st, ev, t.project_ms[i]));
-        if (t.project_ms[i] < best) {
-            best = t.project_ms[i];
-            t.project_rows = PJ_SHAPES[i];
+    t.project_tile_cols = G->g.pj_wc;
+    t.project_waves = G->g.pj_ty;
+    for (int a = 0; a < 4; ++a) {
+        for (int i = 0; i < 4; ++i) {
+            g.pj_wc = WC_SHAPES[a];
+            g.pj_ty = PJ_SHAPES[i];
+            TVR_TRY(time_launches(
+                [&] {
+                    return launch_project<T>(g, x, xt, b, y, nullptr, part, G->pstride, st,
+                                             nullptr);
+                },
+                reps, st, ev, t.project_ms[a][i]));
+            if (t.project_ms[a][i] < best) {
+                best = t.project_ms[a][i];
+                t.project_tile_cols = WC_SHAPES[a];
+                t.project_waves = PJ_SHAPES[i];
+            }
         }
     }
     best = INFINITY;
@@ -91,7 +99,8 @@ tvreg_status tune_impl(tvreg_geometry *G, char *ws, int reps, tvreg_tuning *out,
             t.backproject_depth = BP_SHAPES[i];
         }
     }
-    G->g.pj_ty = t.project_rows;
+    G->g.pj_wc = t.project_tile_cols;
+    G->g.pj_ty = t.project_waves;
     G->g.bp_cz = t.backproject_depth;
     if (out)
         *out = t;
@@ -134,7 +143,8 @@ extern "C" tvreg_status tvreg_get_tuning(const tvreg_geometry *G, tvreg_tuning *
     if (!G || !out)
         return fail(TVREG_EINVAL, "NULL geometry or output");
     *out = tvreg_tuning{};
-    out->project_rows = G->g.pj_ty;
+    out->project_tile_cols = G->g.pj_wc;
+    out->project_waves = G->g.pj_ty;
     out->backproject_depth = G->g.bp_cz;
     return TVREG_OK;
 }
@@ -144,12 +154,16 @@ extern "C" tvreg_status tvreg_set_tuning(tvreg_geometry *G, const tvreg_tuning *
     clear_error();
     if (!G || !t)
         return fail(TVREG_EINVAL, "NULL geometry or tuning");
-    if (!valid_rows(t->project_rows))
-        return fail(TVREG_EINVAL, "project_rows must be 1, 2, 4 or 8, got %d", t->project_rows);
+    if (!valid_cols(t->project_tile_cols))
+        return fail(TVREG_EINVAL, "project_tile_cols must be 8, 16, 32 or 64, got %d",
+                    t->project_tile_cols);
+    if (!valid_waves(t->project_waves))
+        return fail(TVREG_EINVAL, "project_waves must be 1, 2, 4 or 8, got %d", t->project_waves);
     if (!valid_depth(t->backproject_depth))
         return fail(TVREG_EINVAL, "backproject_depth must be 4, 8 or 16, got %d",
                     t->backproject_depth);
-    G->g.pj_ty = t->project_rows;
+    G->g.pj_wc = t->project_tile_cols;
+    G->g.pj_ty = t->project_waves;
     G->g.bp_cz = t->backproject_depth;
     return TVREG_OK;
 }

@@ -54,11 +54,13 @@ struct GeomDev {
     const RowEntry *row;       // [rows]
     const double *dnorm;       // |D|: cone [rows * cols], parallel [nviews]
     MatDev mat;                // stored A^T when present
-    int pj_ty;                 // projector: detector rows per block of 64 columns (1, 2, 4, 8)
+    int pj_wc;                 // projector: detector columns of a wave's ray tile (8, 16, 32, 64)
+    int pj_ty;                 // projector: ray tiles (waves) per block, stacked along rows (1, 2, 4, 8)
     int bp_cz;                 // on-the-fly backprojector: voxels per thread along z (4, 8, 16)
 };
 
 // default tile shapes (the batched solve always uses these)
+constexpr int PJ_WC_DEFAULT = 64;
 constexpr int PJ_TY_DEFAULT = 4;
 constexpr int BP_CZ_DEFAULT = 8;
 

@@ -1,10 +1,11 @@
 """Tile-shape tuning of the on-the-fly operators (tvreg_autotune,
 tvreg_set_tuning).
 
-* Every projector shape (1, 2, 4, 8 detector rows per block) and every
-  backprojector depth (4, 8, 16 voxels per thread along z) gives bitwise the
-  same outputs as the defaults, and those match the oracle (the operator
-  parity tests' bar), on every test geometry and both precisions.
+* Every projector shape (ray tiles of 8 x 8, 16 x 4, 32 x 2, 64 x 1 pixels
+  per wave; 1, 2, 4, 8 waves per block) and every backprojector depth (4, 8,
+  16 voxels per thread along z) gives bitwise the same outputs as the
+  defaults, and those match the oracle (the operator parity tests' bar), on
+  every test geometry and both precisions.
 * The tuner returns a listed shape with positive timings and keeps it.
 * A solve under a non-default shape still matches the oracle's iterations.
 * The batched solve ignores the geometry's shapes.
@@ -29,7 +30,7 @@ def test_every_shape_gives_identical_operators(name, prec):
     print(f"shapes {name} prec={prec}", flush=True)
     g = GEOMS[name]
     G = tv.Geometry(g, prec)
-    assert G.tuning == (4, 8)
+    assert G.tuning == (64, 4, 8)
     rng = np.random.default_rng(51)
     x = rounded(rng.uniform(0.0, 1.0, (g.nz, g.ny, g.nx)), prec)
     r = rounded(rng.standard_normal(g.proj_shape), prec)
@@ -38,12 +39,14 @@ def test_every_shape_gives_identical_operators(name, prec):
     check_close(y0, oracle.project(g, x), prec, f"A x [{name}]")
     if prec == tv.F64:
         check_close(b0, oracle.backproject(g, r), prec, f"A^T r [{name}]")
-    for rows in tv.PROJECT_ROWS:
-        for depth in tv.BACKPROJECT_DEPTHS:
-            G.set_tuning(rows, depth)
-            assert G.tuning == (rows, depth)
-            assert torch.equal(tv.project(G, xd), y0), (rows, depth)
-            assert torch.equal(tv.backproject(G, rd), b0), (rows, depth)
+    for cols in tv.PROJECT_TILE_COLS:
+        for waves in tv.PROJECT_WAVES:
+            G.set_tuning(cols, waves, 8)
+            assert G.tuning == (cols, waves, 8)
+            assert torch.equal(tv.project(G, xd), y0), (cols, waves)
+    for depth in tv.BACKPROJECT_DEPTHS:
+        G.set_tuning(64, 4, depth)
+        assert torch.equal(tv.backproject(G, rd), b0), depth
 
 
 @pytest.mark.parametrize("prec", [tv.F32, tv.F64])
@@ -52,13 +55,15 @@ def test_autotune_picks_a_listed_shape(prec):
     G = tv.Geometry(g, prec)
     t = G.autotune(reps=3)
     print(f"autotune cone64 prec={prec}: {t}", flush=True)
-    assert t["project_rows"] in tv.PROJECT_ROWS
+    assert t["project_tile_cols"] in tv.PROJECT_TILE_COLS
+    assert t["project_waves"] in tv.PROJECT_WAVES
     assert t["backproject_depth"] in tv.BACKPROJECT_DEPTHS
-    assert all(v > 0 for v in t["project_ms"].values())
+    assert len(t["project_ms"]) == 16 and all(v > 0 for v in t["project_ms"].values())
     assert all(v > 0 for v in t["backproject_ms"].values())
-    assert t["project_ms"][t["project_rows"]] == min(t["project_ms"].values())
+    chosen = (t["project_tile_cols"], t["project_waves"])
+    assert t["project_ms"][chosen] == min(t["project_ms"].values())
     assert t["backproject_ms"][t["backproject_depth"]] == min(t["backproject_ms"].values())
-    assert G.tuning == (t["project_rows"], t["backproject_depth"])
+    assert G.tuning == chosen + (t["backproject_depth"],)
     x = to_dev(np.random.default_rng(52).uniform(0, 1, (g.nz, g.ny, g.nx)), prec)
     assert torch.equal(tv.project(G, x), tv.project(tv.Geometry(g, prec), x))
 
@@ -74,7 +79,7 @@ def test_autotune_with_stored_matrix_times_on_the_fly_shapes():
     assert torch.equal(tv.backproject(G, r), before)  # still the stored product
 
 
-@pytest.mark.parametrize("shape", [(1, 16), (8, 4)])
+@pytest.mark.parametrize("shape", [(8, 1, 16), (16, 8, 4), (32, 2, 8)])
 def test_solve_under_other_shapes_matches_oracle_fp64(shape):
     w = synth.cfg_small_parallel()
     og = oracle.Geometry(w.geom)
@@ -100,19 +105,21 @@ def test_batched_solve_ignores_tuning():
     G0 = tv.Geometry(w.geom, tv.F32)
     x0, i0, _ = tv.solve_batched([G0], [b], [p])
     G = tv.Geometry(w.geom, tv.F32)
-    G.set_tuning(1, 16)
+    G.set_tuning(8, 1, 16)
     x1, i1, _ = tv.solve_batched([G], [b], [p])
     assert torch.equal(x1[0], x0[0])
     assert i1[0]["iters"] == i0[0]["iters"]
-    assert G.tuning == (1, 16)
+    assert G.tuning == (8, 1, 16)
 
 
-@pytest.mark.parametrize("rows,depth", [(3, 8), (0, 8), (16, 8), (4, 2), (4, 32), (4, -8)])
-def test_set_tuning_rejects_unlisted_shapes(rows, depth):
+@pytest.mark.parametrize("shape", [(64, 3, 8), (64, 0, 8), (64, 16, 8), (64, 4, 2),
+                                   (64, 4, 32), (64, 4, -8), (4, 4, 8), (128, 4, 8),
+                                   (48, 4, 8), (0, 4, 8)])
+def test_set_tuning_rejects_unlisted_shapes(shape):
     G = tv.Geometry(GEOMS["cone8"], tv.F32)
     with pytest.raises(tv.TvregError, match="must be"):
-        G.set_tuning(rows, depth)
-    assert G.tuning == (4, 8)
+        G.set_tuning(*shape)
+    assert G.tuning == (64, 4, 8)
 
 
 def test_autotune_rejects_bad_reps():
