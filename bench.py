@@ -19,7 +19,12 @@ around each launch of the timed solve), the dominant kernel's roofline, the
 32-problem batch and the differentiated 64^3 form, and the FP64 CPU oracle's
 gradient-evaluation rate on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--fp64] [--gp64-iters N]
+Before the timed region the tile shapes of the on-the-fly operators are
+autotuned on the workload (the choice is reported), and a 1 GiB device copy
+measures the attainable HBM rate for the roofline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--fp64] [--methods]
+                       [--gp64-iters N]
 """
 from __future__ import annotations
 
@@ -82,6 +87,43 @@ def kernel_model(name: str, N: int, m: int, nnz: int, es: int, stored: bool):
     if name == "transpose":
         return "hbm", es * 2.0 * N, "GB/s", HBM_PEAK       # volume in, y-fastest copy out
     raise KeyError(name)
+
+
+def copy_bandwidth(torch, dev, reps: int = 10) -> float:
+    """Device-to-device copy of 1 GiB timed with HIP events: the attainable
+    HBM rate (GB/s, bytes read plus written) beside the spec-sheet peak."""
+    src = torch.ones(2**28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * src.numel() * 4 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    return gbs
+
+
+def grad_eval_loop(tv, torch, G, b, x, w, n: int = 100, runs: int = 5) -> dict:
+    """n back-to-back evaluations of phi and grad phi (tvreg_objective_grad)
+    at x, timed with HIP events; the median over runs."""
+    ws = tv.objective_workspace(G)
+    g = G.empty_volume()
+    tv.objective_grad(G, b, w.alpha, w.tau, x, grad=g, workspace=ws)
+    rates = []
+    for _ in range(runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            tv.objective_grad(G, b, w.alpha, w.tau, x, grad=g, workspace=ws)
+        e1.record()
+        e1.synchronize()
+        rates.append(n / (e0.elapsed_time(e1) / 1e3))
+    rates.sort()
+    return {"evals": n, "runs": runs, "grad_evals_per_s": round(rates[len(rates) // 2], 3),
+            "ms_per_eval": round(1e3 / rates[len(rates) // 2], 4)}
 
 
 def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool):
@@ -171,6 +213,11 @@ def main() -> int:
                     help="first copy 1 GiB device to device (a plain copy of known size that "
                          "scales hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default tile shapes instead of autotuning them")
+    ap.add_argument("--methods", action="store_true",
+                    help="also time GP and GPBB (FP32 and FP64) to tolerance")
+    ap.add_argument("--methods-max-iter", type=int, default=3000)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -222,6 +269,25 @@ def main() -> int:
         matrix = {"gib": round(G32.matrix_bytes / 2**30, 3), "nnz": mnnz,
                   "build_s": round(time.perf_counter() - m0, 3)}
 
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+    tuning = None
+    if not args.no_tune:
+        log("autotuning the on-the-fly operators' tile shapes")
+        t = G32.autotune(reps=5)
+        G64.set_tuning(*G32.tuning)
+        tuning = {"project_tile_cols": t["project_tile_cols"],
+                  "project_waves": t["project_waves"],
+                  "backproject_depth": t["backproject_depth"],
+                  "project_ms": round(t["project_ms"][(t["project_tile_cols"],
+                                                       t["project_waves"])], 4),
+                  "project_ms_default_shape": round(t["project_ms"][(64, 4)], 4),
+                  "project_ms_8x8_tiles": round(min(v for (c, _), v in t["project_ms"].items()
+                                                    if c == 8), 4),
+                  "backproject_on_the_fly_ms": round(t["backproject_ms"][t["backproject_depth"]],
+                                                     4)}
+        log(f"  {tuning}")
+
     log(f"warmup: {args.warmup} UPN iterations")
     xw, iw, _ = tv.solve(G32, b32, method=tv.UPN, eps=0.0, max_iter=max(args.warmup, 1),
                          workspace=ws32, **common)
@@ -258,6 +324,9 @@ def main() -> int:
     roofline = {"kernel": dom, "bound": bound, "achieved": round(amount / avg_s / scale, 3),
                 "peak": peak / scale, "unit": unit, "frac": round(amount / avg_s / peak, 4),
                 "traffic": measured_traffic(dom, stored)}
+    if bound == "hbm":
+        roofline["copy_peak"] = round(copy_gbs, 1)
+        roofline["frac_of_copy"] = round(amount / avg_s / 1e9 / copy_gbs, 4)
     if roofline["traffic"] is not None:
         roofline["traffic_unit"] = "GB per launch"
         roofline["algorithmic"] = round(amount / 1e9, 3)
@@ -279,6 +348,14 @@ def main() -> int:
     }
     if matrix:
         result["stored_transpose"] = matrix
+    if tuning:
+        result["tuning"] = tuning
+    result["hbm_copy_GBps"] = round(copy_gbs, 1)
+
+    if not args.no_legs:
+        log("100 gradient evaluations at x_true (median of 5)")
+        result["grad_eval_loop"] = grad_eval_loop(tv, torch, G32, b32, x_true.float(), w)
+        log(f"  {result['grad_eval_loop']}")
 
     if stored and not args.no_legs:
         log(f"same solve with every operator on the fly: {args.steps} UPN iterations")
@@ -322,6 +399,27 @@ def main() -> int:
         log("differentiated form: 64^3, K = 30")
         result["unrolled64"] = unrolled_leg(tv, synth, torch, dev)
         log(f"  {result['unrolled64']}")
+    if args.methods:
+        for meth, name in ((tv.GPBB, "gpbb"), (tv.GP, "gp")):
+            for label, G, bb in (("f32", G32, b32), ("f64", G64, b64)):
+                log(f"time to tolerance {args.tol:g}: {name} {label}")
+                if label == "f64" and stored:
+                    G.attach_matrix()
+                ws = tv.solve_workspace(G, meth)
+                torch.cuda.synchronize()
+                s0 = time.perf_counter()
+                xs, info, _ = tv.solve(G, bb, method=meth, eps=args.tol,
+                                       max_iter=args.methods_max_iter, workspace=ws, **common)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - s0
+                result[f"time_to_tol_{name}_{label}"] = {
+                    "seconds": round(dt, 3), "iters": info["iters"],
+                    "grad_evals": info["grad_evals"], "func_evals": info["func_evals"],
+                    "gm_rel": info["gm_rel"], "status": info["stop_reason"]}
+                log(f"  {dt:.2f} s, {info['iters']} iterations, status {info['stop_reason']}")
+                del ws
+                if label == "f64" and stored:
+                    G.detach_matrix()
     if args.gp64_iters > 0:
         log(f"GP FP64 for up to {args.gp64_iters} iterations")
         ws = tv.solve_workspace(G64, tv.GP)

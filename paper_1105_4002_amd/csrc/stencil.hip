@@ -65,19 +65,49 @@ __device__ __forceinline__ C huber_bregman(C a0, C a1, C a2, C b0, C b1, C b2, C
 
 // One z-plane of a volume staged in LDS: columns [x0 - o, x0 - o + W) x
 // rows [y0 - o, y0 - o + H) of plane z, zero outside the volume; all the
-// block's threads take part.
+// block's threads take part.  The plane passes through registers so that its
+// global loads can be issued before the block's work on the current plane
+// and written to LDS after it (load_plane, then store_plane).
+template <typename T, int H, int W>
+struct PlaneRegs {
+    static constexpr int E = (H * W + VX * VY - 1) / (VX * VY);  // elements per thread
+    T v[E];
+};
+
+template <typename T, int H, int W>
+__device__ __forceinline__ void load_plane(const T *__restrict__ v, int nx, int ny, int x0, int y0,
+                                           int o, int z, PlaneRegs<T, H, W> &r)
+{
+    const size_t plane = (size_t)nx * ny * z;
+#pragma unroll
+    for (int k = 0; k < PlaneRegs<T, H, W>::E; ++k) {
+        const int e = thread_linear_id() + k * VX * VY;
+        const int ty = e / W, tx = e - ty * W;
+        const int gx = x0 - o + tx, gy = y0 - o + ty;
+        r.v[k] = (e < H * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                     ? v[plane + (size_t)gy * nx + gx]
+                     : T(0);
+    }
+}
+
+template <typename T, int H, int W>
+__device__ __forceinline__ void store_plane(const PlaneRegs<T, H, W> &r, T (&tile)[H][W])
+{
+#pragma unroll
+    for (int k = 0; k < PlaneRegs<T, H, W>::E; ++k) {
+        const int e = thread_linear_id() + k * VX * VY;
+        if (e < H * W)
+            tile[e / W][e % W] = r.v[k];
+    }
+}
+
 template <typename T, int H, int W>
 __device__ __forceinline__ void stage_plane(const T *__restrict__ v, int nx, int ny, int x0,
                                             int y0, int o, int z, T (&tile)[H][W])
 {
-    const size_t plane = (size_t)nx * ny * z;
-    for (int e = thread_linear_id(); e < H * W; e += VX * VY) {
-        const int ty = e / W, tx = e - ty * W;
-        const int gx = x0 - o + tx, gy = y0 - o + ty;
-        tile[ty][tx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-                           ? v[plane + (size_t)gy * nx + gx]
-                           : T(0);
-    }
+    PlaneRegs<T, H, W> r;
+    load_plane(v, nx, ny, x0, y0, o, z, r);
+    store_plane(r, tile);
 }
 
 // gout = (gin ? gin : 0) + alpha grad T(y); with partials also the sums
@@ -115,19 +145,29 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
         const T dz = y[jb + sz] - yb;
         qz_prev = dz * SM<T>::inv_clamped(dx * dx + dy * dy + dz * dz, ct, itau);
     }
+    // planes z and z + 1 sit in the two buffers while plane z is worked on;
+    // plane z + 2 is loaded meanwhile and replaces plane z afterwards
     int cur = 0;
     stage_plane(y, nx, ny, x0, y0, 1, z0, ys[0]);
     if (xref)
         stage_plane(xref, nx, ny, x0, y0, 0, z0, xs[0]);
+    if (z0 + 1 < nz) {
+        stage_plane(y, nx, ny, x0, y0, 1, z0 + 1, ys[1]);
+        if (xref)
+            stage_plane(xref, nx, ny, x0, y0, 0, z0 + 1, xs[1]);
+    }
+    PlaneRegs<T, VY + 2, VX + 2> ry;
+    PlaneRegs<T, VY + 1, VX + 1> rx;
     for (int z = z0; z < z1; ++z) {
         const int nxt = cur ^ 1;
         const bool hz = z + 1 < nz;
-        if (hz) {  // block-uniform
-            stage_plane(y, nx, ny, x0, y0, 1, z + 1, ys[nxt]);
-            if (xref)
-                stage_plane(xref, nx, ny, x0, y0, 0, z + 1, xs[nxt]);
-        }
+        const bool pre = z + 2 < nz && z + 2 <= z1;  // block-uniform: plane z + 2 is needed
         __syncthreads();
+        if (pre) {
+            load_plane(y, nx, ny, x0, y0, 1, z + 2, ry);
+            if (xref)
+                load_plane(xref, nx, ny, x0, y0, 0, z + 2, rx);
+        }
         if (active) {
             const T(&Y)[VY + 2][VX + 2] = ys[cur];
             const T(&Yn)[VY + 2][VX + 2] = ys[nxt];
@@ -179,7 +219,12 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
                 }
             }
         }
-        __syncthreads();  // the next plane overwrites this one's buffer
+        __syncthreads();  // every read of plane z is done: its buffer takes plane z + 2
+        if (pre) {
+            store_plane(ry, ys[cur]);
+            if (xref)
+                store_plane(rx, xs[cur]);
+        }
         cur = nxt;
     }
     if (partials) {
