@@ -273,15 +273,17 @@ __global__ __launch_bounds__(VX *VY) void tv_grouped(BatchProblem<T> *probs, con
 }
 
 template <typename T>
-__device__ __forceinline__ T pstep(const T *__restrict__ z, const T *__restrict__ g, size_t k,
-                                   double step)
+__device__ __forceinline__ T pstep(T z, T g, double step)
 {
-    return (T)fmax((double)z[k] - step * (double)g[k], 0.0);
+    return (T)fmax((double)z - step * (double)g, 0.0);
 }
 
 // xbar = P_Q(z - step g) (Q = nonnegative orthant) with the sums |xbar - z|^2,
 // g^T (z - xbar), T(xbar), Bregman_T(xbar, z) and, for gm_step > 0,
-// |z - P_Q(z - gm_step g)|^2 (the GPBB gradient map).
+// |z - P_Q(z - gm_step g)|^2 (the GPBB gradient map).  Planes of z and g
+// (with the high-side halo the forward differences need) are staged in LDS
+// as in the TV stencil, two buffers deep with the plane after next loaded
+// into registers while the current one is worked on.
 template <typename T>
 __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
                                             const T *__restrict__ zv, const T *__restrict__ g,
@@ -289,27 +291,47 @@ __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
                                             double *__restrict__ partials, int pstride, int bx,
                                             int by, int bz, int bid)
 {
-    const int ix = bx * VX + threadIdx.x;
-    const int iy = by * VY + threadIdx.y;
+    __shared__ T zs[2][VY + 1][VX + 1];  // x in [x0, x0 + VX], y in [y0, y0 + VY]
+    __shared__ T gs[2][VY + 1][VX + 1];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x0 = bx * VX, y0 = by * VY;
+    const int ix = x0 + tx, iy = y0 + ty;
     const int z0 = bz * VZ;
     const int z1 = min(z0 + VZ, nz);
+    const bool active = ix < nx && iy < ny;
     double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (ix < nx && iy < ny) {
-        const T ct = (T)tau, itau = T(1) / ct;
-        const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-        const bool hx = ix + 1 < nx, hy = iy + 1 < ny;
-        size_t j = (size_t)ix + sy * iy + sz * z0;
-        T xj = pstep(zv, g, j, step), zj = zv[j];
-        for (int z = z0; z < z1; ++z, j += sz) {
-            const bool hz = z + 1 < nz;
-            const T gj = g[j];
-            const T xxp = hx ? pstep(zv, g, j + 1, step) : xj;
-            const T zxp = hx ? zv[j + 1] : zj;
-            const T xyp = hy ? pstep(zv, g, j + sy, step) : xj;
-            const T zyp = hy ? zv[j + sy] : zj;
-            const T xzp = hz ? pstep(zv, g, j + sz, step) : xj;
-            const T zzp = hz ? zv[j + sz] : zj;
-            xbar[j] = xj;
+    const T ct = (T)tau, itau = T(1) / ct;
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    const bool hx = ix + 1 < nx, hy = iy + 1 < ny;
+    int cur = 0;
+    stage_plane(zv, nx, ny, x0, y0, 0, z0, zs[0]);
+    stage_plane(g, nx, ny, x0, y0, 0, z0, gs[0]);
+    if (z0 + 1 < nz) {
+        stage_plane(zv, nx, ny, x0, y0, 0, z0 + 1, zs[1]);
+        stage_plane(g, nx, ny, x0, y0, 0, z0 + 1, gs[1]);
+    }
+    PlaneRegs<T, VY + 1, VX + 1> rz, rg;
+    for (int z = z0; z < z1; ++z) {
+        const int nxt = cur ^ 1;
+        const bool hz = z + 1 < nz;
+        const bool pre = z + 2 < nz && z + 2 <= z1;  // block-uniform
+        __syncthreads();
+        if (pre) {
+            load_plane(zv, nx, ny, x0, y0, 0, z + 2, rz);
+            load_plane(g, nx, ny, x0, y0, 0, z + 2, rg);
+        }
+        if (active) {
+            const T(&Z)[VY + 1][VX + 1] = zs[cur];
+            const T(&Gc)[VY + 1][VX + 1] = gs[cur];
+            const T zj = Z[ty][tx], gj = Gc[ty][tx];
+            const T xj = pstep(zj, gj, step);
+            const T zxp = hx ? Z[ty][tx + 1] : zj;
+            const T xxp = hx ? pstep(zxp, Gc[ty][tx + 1], step) : xj;
+            const T zyp = hy ? Z[ty + 1][tx] : zj;
+            const T xyp = hy ? pstep(zyp, Gc[ty + 1][tx], step) : xj;
+            const T zzp = hz ? zs[nxt][ty][tx] : zj;
+            const T xzp = hz ? pstep(zzp, gs[nxt][ty][tx], step) : xj;
+            xbar[(size_t)ix + sy * iy + sz * z] = xj;
             const double ed = (double)xj - (double)zj;
             red[0] += ed * ed;
             red[1] -= (double)gj * ed;
@@ -324,9 +346,13 @@ __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
                 const double p = zd - fmax(zd - gm_step * (double)gj, 0.0);
                 red[4] += p * p;
             }
-            xj = xzp;  // the next plane's own values
-            zj = zzp;
         }
+        __syncthreads();  // every read of plane z is done: its buffers take plane z + 2
+        if (pre) {
+            store_plane(rz, zs[cur]);
+            store_plane(rg, gs[cur]);
+        }
+        cur = nxt;
     }
     const int slots[5] = {S_XD2, S_GD, S_TVB, S_BRB, S_GM2};
     block_reduce_store<5>(red, partials, pstride, slots, bid);
