@@ -102,10 +102,10 @@ tvreg_status tvreg_backproject(const tvreg_geometry *geom, const void *r_dev, vo
  * ray/voxel length from the geometry on the fly.  A geometry can instead
  * hold A^T in caller-owned device memory, voxel-major, built once by the
  * same enumeration and crossing formula (each length rounded once to T), and
- * stream it: tvreg_backproject, tvreg_objective_grad, tvreg_solve and the
- * unrolled solver then use it.  The forward projector always walks the rays
- * on the fly (cheaper than streaming a ray-major copy); tvreg_solve_batched
- * always evaluates on the fly.
+ * stream it: tvreg_backproject, tvreg_objective_grad, tvreg_solve,
+ * tvreg_solve_batched (per problem) and the unrolled solver then use it.
+ * The forward projector always walks the rays on the fly (cheaper than
+ * streaming a ray-major copy).
  *
  * tvreg_matrix_plan counts the entries (GPU pass; needs scratch of
  * tvreg_matrix_scratch_bytes) and returns the bytes tvreg_matrix_attach will

@@ -154,7 +154,7 @@ template hipError_t launch_control_batched<double>(BatchProblem<double> *, int, 
 namespace {
 
 // Kernel families of a round, each with its own prefix table of block counts.
-enum Family : int { F_BP = 0, F_VOX, F_TR, F_PJ, F_EX, F_COUNT };
+enum Family : int { F_BP = 0, F_SP, F_VOX, F_TR, F_PJ, F_EX, F_COUNT };
 
 // Per-problem region: X, XB, YB, G, XT (N values each), RX, RXB, RYB (m
 // each), the partial-sum slots and the finalised sums.
@@ -196,10 +196,10 @@ size_t batch_bytes(int n, const tvreg_geometry *const *geoms, std::vector<size_t
 }
 
 // grouped launches use the default tile shapes whatever the geometry's tuning
+// (a stored transpose, when attached, is used)
 GeomDev default_shapes(const GeomDev &g0)
 {
     GeomDev g = g0;
-    g.mat = MatDev{};  // and evaluate the operators on the fly
     g.pj_wc = PJ_WC_DEFAULT;
     g.pj_ty = PJ_TY_DEFAULT;
     g.bp_cz = BP_CZ_DEFAULT;
@@ -211,7 +211,9 @@ int family_blocks(const tvreg_geometry *G, int f)
     const GeomDev g = default_shapes(G->g);
     switch (f) {
     case F_BP:
-        return backproject_blocks(g);
+        return g.mat.present ? 0 : backproject_blocks(g);
+    case F_SP:
+        return g.mat.present ? matrix_product_blocks(g) : 0;
     case F_VOX:
         return max_reduce_blocks_vol(g.nx, g.ny, g.nz);
     case F_TR:
@@ -330,7 +332,11 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
     } guard{cs};
     auto fam = [&](int f) { return doffs + (size_t)f * (n + 1); };
     TVR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_backproject_grouped<T>(dprobs, fam(F_BP), n, total[F_BP], cs);
+    hipError_t le = hipSuccess;
+    if (total[F_BP] > 0)
+        le = launch_backproject_grouped<T>(dprobs, fam(F_BP), n, total[F_BP], cs);
+    if (le == hipSuccess && total[F_SP] > 0)
+        le = launch_spmv_grouped<T>(dprobs, fam(F_SP), n, total[F_SP], cs);
     if (le == hipSuccess)
         le = launch_tv_grouped<T>(dprobs, fam(F_VOX), n, total[F_VOX], cs);
     if (le == hipSuccess)

@@ -20,6 +20,7 @@
 // gather's enumeration, rounded once to T.  The product accumulates in
 // double.
 #include "gather.hpp"
+#include "reduce.hpp"
 #include "tvreg_internal.hpp"
 
 namespace tvr {
@@ -130,13 +131,13 @@ __global__ __launch_bounds__(CT_TX *CT_TY) void fill_voxels_kernel(GeomDev g, T 
 
 // ---------------------------------------------------------- sparse products
 
-// x = A^T r, one thread per voxel
+// x = A^T r, one thread per voxel; block `blk` of the product
 template <typename T>
-__global__ __launch_bounds__(MB) void spmv_voxels_kernel(GeomDev g, const T *__restrict__ r,
-                                                         T *__restrict__ out)
+__device__ __forceinline__ void spmv_voxels_block(const GeomDev &g, const T *__restrict__ r,
+                                                  T *__restrict__ out, int blk)
 {
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t j = (int64_t)blockIdx.x * MB + threadIdx.x;
+    const int64_t j = (int64_t)blk * MB + threadIdx.x;
     const int64_t s = j >> 6;
     if (s >= g.mat.sv)
         return;
@@ -156,9 +157,38 @@ __global__ __launch_bounds__(MB) void spmv_voxels_kernel(GeomDev g, const T *__r
         out[j] = (T)acc;
 }
 
+template <typename T>
+__global__ __launch_bounds__(MB) void spmv_voxels_kernel(GeomDev g, const T *__restrict__ r,
+                                                         T *__restrict__ out)
+{
+    spmv_voxels_block<T>(g, r, out, blockIdx.x);
+}
+
+// Batched: G = A^T RY for every problem with a stored transpose whose
+// gradient is due this round.
+template <typename T>
+__global__ __launch_bounds__(MB) void spmv_grouped(BatchProblem<T> *probs, const int *offs, int n)
+{
+    const int p = find_problem(offs, n, blockIdx.x);
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING || !P.need_grad)
+        return;
+    spmv_voxels_block<T>(P.g, P.RY, P.G, blockIdx.x - offs[p]);
+}
+
 int blocks_for(int64_t n) { return (int)((n + MB - 1) / MB); }
 
 }  // namespace
+
+int matrix_product_blocks(const GeomDev &g) { return blocks_for((int64_t)g.nx * g.ny * g.nz); }
+
+template <typename T>
+hipError_t launch_spmv_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL((spmv_grouped<T>), dim3(blocks), dim3(MB), 0, st, probs, offs, n);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_backproject_matrix(const GeomDev &g, const T *r, T *out, hipStream_t st)
@@ -203,7 +233,9 @@ hipError_t launch_matrix_fill(const GeomDev &g, T *val_v, int32_t *idx_v, hipStr
 #define TVR_INST_MAT(T)                                                                          \
     template hipError_t launch_backproject_matrix<T>(const GeomDev &, const T *, T *,            \
                                                      hipStream_t);                               \
-    template hipError_t launch_matrix_fill<T>(const GeomDev &, T *, int32_t *, hipStream_t);
+    template hipError_t launch_matrix_fill<T>(const GeomDev &, T *, int32_t *, hipStream_t);     \
+    template hipError_t launch_spmv_grouped<T>(BatchProblem<T> *, const int *, int, int,        \
+                                               hipStream_t);
 
 TVR_INST_MAT(float)
 TVR_INST_MAT(double)

@@ -217,6 +217,11 @@ struct BatchProblem {
 template <typename T>
 hipError_t launch_backproject_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                                       hipStream_t st);
+// the problems with a stored transpose (the on-the-fly kernel above takes the others)
+template <typename T>
+hipError_t launch_spmv_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                               hipStream_t st);
+int matrix_product_blocks(const GeomDev &g);
 template <typename T>
 hipError_t launch_tv_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                              hipStream_t st);
