@@ -126,9 +126,11 @@ def grad_eval_loop(tv, torch, G, b, x, w, n: int = 100, runs: int = 5) -> dict:
             "ms_per_eval": round(1e3 / rates[len(rates) // 2], 4)}
 
 
-def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool):
+def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool,
+              stored: bool = False):
     """The 32-problem batch (uneven sizes, views and alphas), FP32 UPN to tol:
-    one tvreg_solve_batched call, and optionally the same problems one by one."""
+    one tvreg_solve_batched call, and optionally the same problems one by one;
+    with `stored`, every problem streams its stored A^T (built beforehand)."""
     ws_ = synth.cfg_batch()
     geoms, bs = [], []
     for w in ws_:
@@ -138,6 +140,14 @@ def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool
         bs.append((ax + sigma * torch.from_numpy(w.unit_noise()).to(dev)).float().contiguous())
         del G64, ax
         geoms.append(tv.Geometry(w.geom, tv.F32))
+    build_s = None
+    if stored:
+        torch.cuda.synchronize()
+        m0 = time.perf_counter()
+        for G in geoms:
+            G.attach_matrix()
+        torch.cuda.synchronize()
+        build_s = round(time.perf_counter() - m0, 3)
     params = [dict(method=tv.UPN, alpha=w.alpha, tau=w.tau, eps=tol, max_iter=max_iter)
               for w in ws_]
     ws = tv.solve_batched_workspace(geoms, dev)
@@ -151,6 +161,9 @@ def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool
            "iters_max": max(i["iters"] for i in infos),
            "grad_evals": int(sum(i["grad_evals"] for i in infos)),
            "converged": int(sum(1 for i in infos if i["stop_reason"] == tv.OK))}
+    if stored:
+        out["stored_transpose_gib"] = round(sum(G.matrix_bytes for G in geoms) / 2**30, 3)
+        out["stored_transpose_build_s"] = build_s
     if sequential:
         t0 = time.perf_counter()
         for G, b, p in zip(geoms, bs, params):
@@ -396,6 +409,10 @@ def main() -> int:
         log("32-problem batch, FP32 UPN to 1e-6")
         result["batch32"] = batch_leg(tv, synth, torch, dev, 1e-6, 5000, args.batch_seq)
         log(f"  {result['batch32']}")
+        log("32-problem batch with stored A^T, FP32 UPN to 1e-6")
+        result["batch32_stored"] = batch_leg(tv, synth, torch, dev, 1e-6, 5000, args.batch_seq,
+                                             stored=True)
+        log(f"  {result['batch32_stored']}")
         log("differentiated form: 64^3, K = 30")
         result["unrolled64"] = unrolled_leg(tv, synth, torch, dev)
         log(f"  {result['unrolled64']}")

@@ -32,6 +32,30 @@ struct RayTile {
     static constexpr int rows = 64 / WC;  // detector rows per wave
 };
 
+// Block order.  Logical block L walks the column blocks of one row band
+// through every view before moving to the next band: the rays of a band
+// cross a thin z-slab of the volume, whatever the view.  The hardware deals
+// consecutive blocks round-robin to the 8 XCDs, each with its own L2; the
+// launch remaps that so each XCD runs a contiguous range of logical blocks,
+// and its L2 holds the slab of its current band instead of the whole
+// volume.  A block's work depends only on L (also the index of its partial
+// sums), so the batched kernel, which numbers blocks without the remap,
+// computes the same values.
+constexpr int N_XCD = 8;
+
+__device__ __forceinline__ int xcd_contiguous(int p, int nb)
+{
+    const int q = nb / N_XCD, rem = nb % N_XCD, k = p % N_XCD;
+    return k * q + min(k, rem) + p / N_XCD;
+}
+
+__device__ __forceinline__ void decode_block(int L, int gx, int nviews, int &bx, int &by, int &v)
+{
+    bx = L % gx;
+    v = (L / gx) % nviews;
+    by = L / (gx * nviews);
+}
+
 // One block: WC detector columns x (TY * 64 / WC) rows of view v.
 template <typename T, bool CONE, int WC, int TY>
 __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restrict__ x,
@@ -78,8 +102,10 @@ __global__ __launch_bounds__(64 * TY) void project_kernel(GeomDev g, const T *__
                                                               double *__restrict__ partials,
                                                               int pstride)
 {
-    project_block<T, CONE, WC, TY>(g, x, xt, b, out, rref, partials, pstride, blockIdx.x,
-                                   blockIdx.y, blockIdx.z, block_linear_id());
+    const int L = xcd_contiguous(blockIdx.x, gridDim.x);
+    int bx, by, v;
+    decode_block(L, (g.cols + WC - 1) / WC, g.nviews, bx, by, v);
+    project_block<T, CONE, WC, TY>(g, x, xt, b, out, rref, partials, pstride, bx, by, v, L);
 }
 
 // Batched: the trial points XB of every running problem (residual against
@@ -93,9 +119,9 @@ __global__ __launch_bounds__(64 * PJ_TY_DEFAULT) void project_grouped(BatchProbl
     if (P.state != B_RUNNING)
         return;
     const int local = blockIdx.x - offs[p];
-    constexpr int WC = PJ_WC_DEFAULT, TY = PJ_TY_DEFAULT, BR = TY * RayTile<WC>::rows;
-    const int gx = (P.g.cols + WC - 1) / WC, gy = (P.g.rows + BR - 1) / BR;
-    const int bx = local % gx, by = (local / gx) % gy, v = local / (gx * gy);
+    constexpr int WC = PJ_WC_DEFAULT, TY = PJ_TY_DEFAULT;
+    int bx, by, v;
+    decode_block(local, (P.g.cols + WC - 1) / WC, P.g.nviews, bx, by, v);
     if (P.g.cone)
         project_block<T, true, WC, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx,
                                        by, v, local);
@@ -132,9 +158,8 @@ template <typename T, int WC, int TY>
 void launch_shape(const GeomDev &g, const T *x, const T *xt, const T *b, T *out, const T *rref,
                   double *partials, int pstride, hipStream_t st)
 {
-    constexpr int BR = TY * RayTile<WC>::rows;
     dim3 block(64, TY, 1);
-    dim3 grid((g.cols + WC - 1) / WC, (g.rows + BR - 1) / BR, g.nviews);
+    dim3 grid(grid_blocks(g, WC, TY), 1, 1);  // decoded in the kernel
     if (g.cone)
         hipLaunchKernelGGL((project_kernel<T, true, WC, TY>), grid, block, 0, st, g, x, xt, b,
                            out, rref, partials, pstride);
