@@ -221,13 +221,23 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
     }
 }
 
+// The hardware deals consecutive blocks round-robin to the 8 XCDs, each with
+// its own L2; the kernel remaps block ids so that each XCD runs a contiguous
+// range of bricks (x fastest, then y, then z): its L2 then serves the
+// detector rows of a few z-chunks instead of every chunk in flight.
+constexpr int N_XCD = 8;
+
 template <typename T, bool CONE, int CZ>
 __global__ __launch_bounds__(BP_THREADS) void backproject_kernel(GeomDev g,
                                                                 const T *__restrict__ r,
                                                                 T *__restrict__ out)
 {
     __shared__ Tile tile;
-    backproject_block<T, CONE, CZ>(g, r, out, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+    const int nb = gridDim.x, p = blockIdx.x;
+    const int q = nb / N_XCD, rem = nb % N_XCD, k = p % N_XCD;
+    const int L = k * q + min(k, rem) + p / N_XCD;
+    const int gx = (g.nx + BP_TX - 1) / BP_TX, gy = (g.ny + BP_TY - 1) / BP_TY;
+    backproject_block<T, CONE, CZ>(g, r, out, L % gx, (L / gx) % gy, L / (gx * gy), tile);
 }
 
 // Batched: G = A^T RY for every problem whose gradient is due this round.
@@ -277,7 +287,9 @@ template <typename T, int CZ>
 static void launch_backproject_cz(const GeomDev &g, const T *r, T *out, hipStream_t st)
 {
     dim3 block(BP_THREADS, 1, 1);
-    dim3 grid((g.nx + BP_TX - 1) / BP_TX, (g.ny + BP_TY - 1) / BP_TY, (g.nz + CZ - 1) / CZ);
+    dim3 grid(((g.nx + BP_TX - 1) / BP_TX) * ((g.ny + BP_TY - 1) / BP_TY) *
+                  ((g.nz + CZ - 1) / CZ),
+              1, 1);
     if (g.cone)
         hipLaunchKernelGGL((backproject_kernel<T, true, CZ>), grid, block, 0, st, g, r, out);
     else
