@@ -44,7 +44,7 @@ HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 # WRITE_SIZE scaled by a 1 GiB copy (profiles/cone256_kernels_hbm_traffic_pmc.md);
 # reported only while the kernel source is the one measured.
 MEASURED_TRAFFIC = {"kernel": "backproject", "source": "paper_1105_4002_amd/csrc/matrix.hip",
-                    "sha256_prefix": "1fac8cd6fbb0b308", "bytes": 12.27e9 + 0.067e9}
+                    "sha256_prefix": "84fca6d7b080f00d", "bytes": 12.266e9 + 0.067e9}
 
 
 def measured_traffic(kernel: str, stored: bool):
@@ -57,6 +57,14 @@ def measured_traffic(kernel: str, stored: bool):
         return None
     return round(MEASURED_TRAFFIC["bytes"] / 1e9, 3)
 FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed math)
+# vector instruction issue: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s
+# vector instructions per voxel step of the projector's walk loop (count of the
+# gfx950 code the build emits for project_kernel: 3 min, 1 compare and the loop
+# exit; 3 compares, 3 selects and 2 adds for the index; 3 adds and 3 FMAs for
+# the next crossings; 12 selects for the plane and crossing updates; length,
+# load address, convert and accumulate)
+PROJECT_VALU_PER_STEP = 39
 
 
 def log(msg: str) -> None:
@@ -330,6 +338,10 @@ def main() -> int:
             kernels[name] = {"launches": cnt, "avg_ms": round(ms / cnt, 4),
                              "total_ms": round(ms, 3), "bound": bound,
                              "frac": round(amount / avg / peak, 4)}
+            if name == "project":
+                # the walk's instruction stream against the chip's issue rate
+                kernels[name]["valu_issue_frac"] = round(
+                    PROJECT_VALU_PER_STEP * nnz / avg / VALU_ISSUE_PEAK, 4)
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     bound, amount, unit, peak = kernel_model(dom, N, m, nnz, 4, stored)
     avg_s = kernels[dom]["avg_ms"] / 1e3
