@@ -13,6 +13,9 @@ entry point       paper passage                           pinned by
 project           A, the system matrix (Sec. II-A)        brute-force slab lengths on 8^3 volumes;
                   (Siddon exact path length, reading)     chord-length closed form; axis-aligned
                                                           ray closed form; single-voxel projection
+                  3D parallel beam over the unit sphere   in-plane directions = parallel beam;
+                  (Sec. IV-A)                             axis directions = oriented column sums;
+                                                          ones -> independent chord lengths
 backproject       A^T (gradient of eq. 1)                 adjoint identity <Ax,y> = <x,A^T y>
                                                           against the dense brute-force matrix
 tv                eq. 2, Huber-smoothed                   closed-form TV of boxes; central finite
@@ -62,7 +65,8 @@ class _Geom(ctypes.Structure):
                 ("n_views", ctypes.c_int32), ("angles", ctypes.POINTER(ctypes.c_double)),
                 ("cone", ctypes.c_int32), ("cols", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("pitch_u", ctypes.c_double), ("pitch_v", ctypes.c_double),
-                ("src_to_centre", ctypes.c_double), ("src_to_det", ctypes.c_double)]
+                ("src_to_centre", ctypes.c_double), ("src_to_det", ctypes.c_double),
+                ("dirs", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Params(ctypes.Structure):
@@ -147,9 +151,18 @@ class Geometry:
     def __init__(self, g):
         self.desc = g
         self._angles = np.ascontiguousarray(np.asarray(g.angles, dtype=np.float64))
+        dirs = getattr(g, "dirs", None)
+        if int(g.beam) == 2:
+            self._dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+            if len(self._dirs) != len(self._angles):
+                raise ValueError("one direction per view is needed")
+            dp = _dp(self._dirs)
+        else:
+            self._dirs = None
+            dp = ctypes.POINTER(ctypes.c_double)()
         self.s = _Geom(g.nx, g.ny, g.nz, len(self._angles), _dp(self._angles), int(g.beam),
                        g.det_cols, g.det_rows, float(g.pitch_u), float(g.pitch_v),
-                       float(g.src_to_centre), float(g.src_to_det))
+                       float(g.src_to_centre), float(g.src_to_det), dp)
         self.vol_shape = (g.nz, g.ny, g.nx)
         self.proj_shape = (len(self._angles), g.det_rows, g.det_cols)
 

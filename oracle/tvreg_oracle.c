@@ -19,7 +19,10 @@
  *   - view angle theta, e_s = (cos, sin, 0), e_u = (-sin, cos, 0), e_v = z;
  *     pixel centre u = (col - (cols-1)/2) pitch_u, w = (row - (rows-1)/2) pitch_v;
  *     parallel beam: the line through u e_u + w e_v with direction e_s;
- *     cone beam: source R e_s, pixel at -(SDD - R) e_s + u e_u + w e_v.
+ *     cone beam: source R e_s, pixel at -(SDD - R) e_s + u e_u + w e_v;
+ *   - parallel beam along given directions d (the paper's 3D parallel beam,
+ *     Sec. IV-A): the line through u e_u + w e_v along d, with
+ *     e_u = (e_z x d)/|e_z x d| (e_x if d is along z) and e_v = d x e_u.
  */
 #include "tvreg_oracle.h"
 
@@ -46,10 +49,41 @@ int32_t og_num_threads(void)
 void og_ray_endpoints(const og_geom *g, int32_t v, int32_t row, int32_t col,
                       double p0[3], double p1[3])
 {
-    double th = g->angles[v];
-    double c = cos(th), s = sin(th);
     double u = ((double)col - 0.5 * (double)(g->cols - 1)) * g->pitch_u;
     double w = ((double)row - 0.5 * (double)(g->rows - 1)) * g->pitch_v;
+    if (g->cone == 2) {
+        /* parallel rays along the view direction d (normalised); the
+           detector plane passes through the origin with axes
+           e_u = (e_z x d) / |e_z x d| (e_x when d runs along z) and
+           e_v = d x e_u, which for d = (cos, sin, 0) are the axes of the
+           parallel beam about z below */
+        const double *q = g->dirs + 3 * (size_t)v;
+        double nd = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        double d[3] = {q[0] / nd, q[1] / nd, q[2] / nd};
+        double eu[3], ev[3];
+        double a = sqrt(d[0] * d[0] + d[1] * d[1]);
+        if (a > 0.0) {
+            eu[0] = -d[1] / a;
+            eu[1] = d[0] / a;
+            eu[2] = 0.0;
+        } else {
+            eu[0] = 1.0;
+            eu[1] = 0.0;
+            eu[2] = 0.0;
+        }
+        ev[0] = d[1] * eu[2] - d[2] * eu[1];
+        ev[1] = d[2] * eu[0] - d[0] * eu[2];
+        ev[2] = d[0] * eu[1] - d[1] * eu[0];
+        double h = (double)(g->nx + g->ny + g->nz);
+        for (int k = 0; k < 3; ++k) {
+            double o = u * eu[k] + w * ev[k];
+            p0[k] = o - h * d[k];
+            p1[k] = o + h * d[k];
+        }
+        return;
+    }
+    double th = g->angles[v];
+    double c = cos(th), s = sin(th);
     if (g->cone) {
         double R = g->src_to_centre, D = g->src_to_det;
         p0[0] = R * c;

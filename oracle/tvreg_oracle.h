@@ -23,11 +23,13 @@ typedef struct {
     int32_t nx, ny, nz;
     int32_t n_views;
     const double *angles;   /* n_views view angles, radians */
-    int32_t cone;           /* 0: parallel beam about z, 1: circular cone beam */
+    int32_t cone;           /* 0: parallel beam about z, 1: circular cone beam,
+                               2: parallel beam along given directions (dirs) */
     int32_t cols, rows;     /* detector pixels */
     double pitch_u, pitch_v;
     double src_to_centre;   /* cone only */
     double src_to_det;      /* cone only */
+    const double *dirs;     /* beam 2: n_views view directions (x, y, z), any length */
 } og_geom;
 
 enum { OG_GP = 0, OG_GPBB = 1, OG_UPN = 2 };

@@ -20,7 +20,11 @@ Conventions (shared definitions of the *inputs*, stated once here):
   volume centred at the origin);
 * projection data has shape (n_views, det_rows, det_cols), column fastest;
 * view angles are theta_v = span * v / n_views (span = pi for parallel beam,
-  2 pi for cone beam), given explicitly as a float64 array.
+  2 pi for cone beam), given explicitly as a float64 array;
+* the 3D parallel beam (PARALLEL3D) takes one direction d per view; its
+  detector plane passes through the origin with axes e_u = (e_z x d) /
+  |e_z x d| (e_x when d is along z) and e_v = d x e_u (for d = (cos, sin, 0)
+  these are the parallel beam's axes); its ``angles`` are only a view count.
 """
 from __future__ import annotations
 
@@ -32,6 +36,7 @@ import numpy as np
 
 PARALLEL = 0
 CONE = 1
+PARALLEL3D = 2  # parallel rays along per-view direction vectors (``dirs``)
 
 
 @dataclasses.dataclass
@@ -49,6 +54,7 @@ class Geometry:
     pitch_v: float = 1.0
     src_to_centre: float = 0.0  # cone only
     src_to_det: float = 0.0  # cone only
+    dirs: Optional[np.ndarray] = None  # PARALLEL3D only: (n_views, 3) float64 directions
 
     @property
     def n_views(self) -> int:
@@ -110,6 +116,28 @@ def cone_geometry(n: int, n_views: int, det_cols: int, det_rows: int,
     a = view_angles(n_views, span) if angles is None else np.asarray(angles, np.float64)
     return Geometry(n, n, n, a, CONE, det_cols, det_rows, pitch, pitch,
                     float(src_to_centre), float(src_to_det))
+
+
+def sphere_directions(n_views: int) -> np.ndarray:
+    """n_views view directions spread evenly over the unit sphere (Sec. IV-A).
+
+    A parallel ray along d and one along -d are the same line, so the
+    directions cover the upper hemisphere: the golden-angle spiral with equal
+    area per direction, z_k = 1 - (k + 1/2) / n_views and longitude
+    k * pi (3 - sqrt 5), k = 0..n_views-1.  Returns (n_views, 3) float64.
+    """
+    k = np.arange(n_views, dtype=np.float64)
+    z = 1.0 - (k + 0.5) / n_views
+    lon = k * (math.pi * (3.0 - math.sqrt(5.0)))
+    r = np.sqrt(1.0 - z * z)
+    return np.ascontiguousarray(np.stack([r * np.cos(lon), r * np.sin(lon), z], axis=1))
+
+
+def parallel3d_geometry(n: int, dirs: np.ndarray, det_cols: int, det_rows: int,
+                        pitch: float = 1.0) -> Geometry:
+    d = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(-1, 3))
+    return Geometry(n, n, n, np.zeros(len(d)), PARALLEL3D, det_cols, det_rows, pitch, pitch,
+                    dirs=d)
 
 
 def ellipsoid_phantom(n: int, n_ellipsoids: int, seed: int) -> np.ndarray:
@@ -196,6 +224,18 @@ def cfg_unrolled() -> Workload:
     n = 64
     g = cone_geometry(n, 30, 96, 96, 1.5, 4 * n, 6 * n)
     return Workload("unrolled64", g, 10, 0.01, 1e-2, 1e-4, 501, 502)
+
+
+def cfg_paper(n_views: int = 55) -> Workload:
+    """The paper's test problem (Sec. IV-A): a 64^3 volume, a parallel beam
+    whose n_views directions are spread over the unit sphere (55: many-view,
+    19: few-view), 91 x 91 detector pixels, 1 % noise, alpha = 1e-2.  The
+    pitch sqrt(3) 64 / 91 makes the detector cover the volume's circumscribed
+    sphere from every direction.  Ten seeded ellipsoids stand in for the
+    FORBILD head phantom."""
+    n = 64
+    g = parallel3d_geometry(n, sphere_directions(n_views), 91, 91, math.sqrt(3.0) * n / 91)
+    return Workload(f"paper{n_views}", g, 10, 0.01, 1e-2, 1e-4, 600 + n_views, 700 + n_views)
 
 
 def fd_direction(shape, seed: int = 503) -> np.ndarray:
