@@ -21,6 +21,12 @@
  *    centre u = (col - (cols-1)/2) pitch_u, w = (row - (rows-1)/2) pitch_v.
  *    Parallel beam: the line through u e_u + w e_v with direction e_s.
  *    Cone beam: the segment from R e_s to -(SDD - R) e_s + u e_u + w e_v.
+ *    3D parallel beam (Sec. IV-A: view directions over the unit sphere):
+ *    view v has the unit direction d = view_dirs[v] / |view_dirs[v]| and the
+ *    detector axes e_u = e_z x d / |e_z x d| (e_x when d runs along z),
+ *    e_v = d x e_u (for d = (cos, sin, 0) the parallel beam's axes); pixel
+ *    (row, col) is the line through u e_u + w e_v along d.  Its A^T is
+ *    evaluated by a voxel-driven gather over the same crossings.
  *  - Precision: TVREG_F32_RED64 stores vectors as float (32-bit) and forms
  *    every inner product, objective value, step length, line-search test and
  *    stop test in double; ray geometry is double in both modes.  TVREG_F64
@@ -51,7 +57,7 @@ typedef enum {
     TVREG_ESTALL = 2     /* a line-search cap was hit; last accepted x returned */
 } tvreg_status;
 
-typedef enum { TVREG_PARALLEL = 0, TVREG_CONE = 1 } tvreg_beam;
+typedef enum { TVREG_PARALLEL = 0, TVREG_CONE = 1, TVREG_PARALLEL_3D = 2 } tvreg_beam;
 typedef enum { TVREG_F32_RED64 = 0, TVREG_F64 = 1 } tvreg_precision;
 typedef enum { TVREG_GP = 0, TVREG_GPBB = 1, TVREG_UPN = 2 } tvreg_method;
 
@@ -59,12 +65,16 @@ typedef enum { TVREG_GP = 0, TVREG_GPBB = 1, TVREG_UPN = 2 } tvreg_method;
 typedef struct {
     int32_t nx, ny, nz;          /* volume size, each >= 1 */
     int32_t n_views;             /* >= 1 */
-    const double *angles_rad;    /* host array of n_views view angles (copied) */
+    const double *angles_rad;    /* host array of n_views view angles (copied);
+                                    unused (may be NULL) for TVREG_PARALLEL_3D */
     tvreg_beam beam;
     int32_t det_cols, det_rows;  /* >= 1 */
     double pitch_u, pitch_v;     /* > 0 */
     double src_to_centre;        /* cone: R, must exceed the volume's half diagonal */
     double src_to_det;           /* cone: SDD, SDD - R must exceed the half diagonal */
+    const double *view_dirs;     /* TVREG_PARALLEL_3D: host array of n_views directions
+                                    (x, y, z), finite and nonzero, normalised and
+                                    copied; ignored by the other beams */
 } tvreg_geometry_desc;
 
 typedef struct tvreg_geometry tvreg_geometry; /* opaque, library-owned */

@@ -14,12 +14,13 @@ import ctypes
 import os
 from typing import Optional
 
+import numpy as np
 import torch  # loads the HIP runtime the library binds to
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtvreg.so")
 
-PARALLEL, CONE = 0, 1
+PARALLEL, CONE, PARALLEL_3D = 0, 1, 2
 F32, F64 = 0, 1
 GP, GPBB, UPN = 0, 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, ESTALL = 0, -1, -2, -3, 1, 2
@@ -33,7 +34,7 @@ class _Desc(ctypes.Structure):
                 ("beam", ctypes.c_int), ("det_cols", ctypes.c_int32),
                 ("det_rows", ctypes.c_int32), ("pitch_u", ctypes.c_double),
                 ("pitch_v", ctypes.c_double), ("src_to_centre", ctypes.c_double),
-                ("src_to_det", ctypes.c_double)]
+                ("src_to_det", ctypes.c_double), ("view_dirs", _c_dp)]
 
 
 class _SolveParams(ctypes.Structure):
@@ -204,10 +205,20 @@ class Geometry:
 
     def __init__(self, desc, precision: int = F32):
         self._angles = (ctypes.c_double * len(desc.angles))(*[float(a) for a in desc.angles])
+        dirs = getattr(desc, "dirs", None)
+        if int(desc.beam) == PARALLEL_3D:
+            flat = [float(v) for v in np.asarray(dirs, dtype=np.float64).reshape(-1)]
+            if len(flat) != 3 * len(desc.angles):
+                raise ValueError("a 3D parallel beam needs one direction per view")
+            self._dirs = (ctypes.c_double * len(flat))(*flat)
+            dp = ctypes.cast(self._dirs, _c_dp)
+        else:
+            self._dirs = None
+            dp = _c_dp()
         d = _Desc(int(desc.nx), int(desc.ny), int(desc.nz), len(desc.angles),
                   ctypes.cast(self._angles, _c_dp), int(desc.beam), int(desc.det_cols),
                   int(desc.det_rows), float(desc.pitch_u), float(desc.pitch_v),
-                  float(desc.src_to_centre), float(desc.src_to_det))
+                  float(desc.src_to_centre), float(desc.src_to_det), dp)
         h = ctypes.c_void_p()
         _check(_lib.tvreg_create_geometry(ctypes.byref(d), int(precision), ctypes.byref(h)),
                "tvreg_create_geometry")

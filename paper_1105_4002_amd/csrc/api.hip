@@ -74,8 +74,11 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->n_views < 1 || d->det_cols < 1 ||
         d->det_rows < 1)
         return fail(TVREG_EINVAL, "sizes must be >= 1");
-    if (!d->angles_rad)
+    const bool p3 = d->beam == TVREG_PARALLEL_3D;
+    if (!p3 && !d->angles_rad)
         return fail(TVREG_EINVAL, "angles_rad is NULL");
+    if (p3 && !d->view_dirs)
+        return fail(TVREG_EINVAL, "view_dirs is NULL for a 3D parallel beam");
     if (!(d->pitch_u > 0) || !(d->pitch_v > 0))
         return fail(TVREG_EINVAL, "detector pitches must be > 0");
     const int64_t N = (int64_t)d->nx * d->ny * d->nz;
@@ -92,12 +95,19 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
                         "cone beam needs source and detector outside the volume's bounding "
                         "sphere (R=%g, SDD=%g, half diagonal %g)",
                         d->src_to_centre, d->src_to_det, half_diag);
-    } else if (d->beam != TVREG_PARALLEL) {
+    } else if (d->beam != TVREG_PARALLEL && !p3) {
         return fail(TVREG_EINVAL, "unknown beam %d", (int)d->beam);
     }
-    for (int v = 0; v < d->n_views; ++v)
-        if (!isfinite(d->angles_rad[v]))
+    for (int v = 0; v < d->n_views; ++v) {
+        if (p3) {
+            const double *q = d->view_dirs + 3 * (size_t)v;
+            if (!isfinite(q[0]) || !isfinite(q[1]) || !isfinite(q[2]) ||
+                !(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] > 0.0))
+                return fail(TVREG_EINVAL, "view direction %d is not finite and nonzero", v);
+        } else if (!isfinite(d->angles_rad[v])) {
             return fail(TVREG_EINVAL, "angle %d is not finite", v);
+        }
+    }
 
     const bool cone = d->beam == TVREG_CONE;
     const int V = d->n_views, C = d->det_cols, Rw = d->det_rows;
@@ -105,10 +115,39 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     const double R = d->src_to_centre, SDD = d->src_to_det;
 
     std::vector<double2> cs(V);
-    std::vector<ColEntry> colt((size_t)V * C);
-    std::vector<RowEntry> rowt(Rw);
+    // the 3D beam forms its rays from per-view tables: one placeholder entry
+    // in the column / row tables, which nothing reads for it
+    std::vector<ColEntry> colt(p3 ? 1 : (size_t)V * C);
+    std::vector<RowEntry> rowt(p3 ? 1 : Rw);
     std::vector<double> dn(cone ? (size_t)Rw * C : (size_t)V);
-    for (int v = 0; v < V; ++v) {
+    std::vector<View3> v3t(p3 ? V : 1);
+    for (int v = 0; p3 && v < V; ++v) {
+        const double *q = d->view_dirs + 3 * (size_t)v;
+        const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        View3 &e = v3t[v];
+        e.dx = q[0] / nq;
+        e.dy = q[1] / nq;
+        e.dz = q[2] / nq;
+        const double a = sqrt(e.dx * e.dx + e.dy * e.dy);  // |e_z x d|
+        if (a > 0.0) {
+            e.ux = -e.dy / a;
+            e.uy = e.dx / a;
+        } else {
+            e.ux = 1.0;
+            e.uy = 0.0;
+        }
+        e.uz = 0.0;
+        // e_v = d x e_u
+        e.vx = e.dy * e.uz - e.dz * e.uy;
+        e.vy = e.dz * e.ux - e.dx * e.uz;
+        e.vz = e.dx * e.uy - e.dy * e.ux;
+        e.idx = e.dx != 0.0 ? 1.0 / e.dx : 0.0;
+        e.idy = e.dy != 0.0 ? 1.0 / e.dy : 0.0;
+        e.idz = e.dz != 0.0 ? 1.0 / e.dz : 0.0;
+        cs[v] = make_double2(e.dx, e.dy);
+        dn[v] = 1.0;  // |d|
+    }
+    for (int v = 0; !p3 && v < V; ++v) {
         const double c = cos(d->angles_rad[v]), s = sin(d->angles_rad[v]);
         cs[v] = make_double2(c, s);
         for (int col = 0; col < C; ++col) {
@@ -133,7 +172,7 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
         if (!cone)
             dn[v] = sqrt(c * c + s * s);
     }
-    for (int row = 0; row < Rw; ++row) {
+    for (int row = 0; !p3 && row < Rw; ++row) {
         const double w = ((double)row - rv0) * d->pitch_v;
         RowEntry &e = rowt[row];
         e.Sz = cone ? 0.0 : w;
@@ -151,7 +190,14 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     if (!G)
         return fail(TVREG_ENOMEM, "host allocation failed");
     G->desc = *d;
-    G->angles.assign(d->angles_rad, d->angles_rad + V);
+    if (p3) {
+        G->angles.assign((size_t)V, 0.0);
+        G->dirs.assign(d->view_dirs, d->view_dirs + 3 * (size_t)V);
+        G->desc.view_dirs = G->dirs.data();
+    } else {
+        G->angles.assign(d->angles_rad, d->angles_rad + V);
+        G->desc.view_dirs = nullptr;
+    }
     G->desc.angles_rad = G->angles.data();
     G->prec = precision;
     G->N = N;
@@ -164,7 +210,8 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     const size_t o_col = align_up(o_cs + sizeof(double2) * V, 256);
     const size_t o_row = align_up(o_col + sizeof(ColEntry) * colt.size(), 256);
     const size_t o_dn = align_up(o_row + sizeof(RowEntry) * rowt.size(), 256);
-    const size_t total = align_up(o_dn + sizeof(double) * dn.size(), 256);
+    const size_t o_v3 = align_up(o_dn + sizeof(double) * dn.size(), 256);
+    const size_t total = align_up(o_v3 + sizeof(View3) * v3t.size(), 256);
     char *base = nullptr;
     if (hipMalloc((void **)&base, total) != hipSuccess) {
         delete G;
@@ -179,6 +226,9 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(base + o_dn, dn.data(), sizeof(double) * dn.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + o_v3, v3t.data(), sizeof(View3) * v3t.size(),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(base);
         delete G;
@@ -208,6 +258,8 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     g.col = (const ColEntry *)(base + o_col);
     g.row = (const RowEntry *)(base + o_row);
     g.dnorm = (const double *)(base + o_dn);
+    g.beam3d = p3 ? 1 : 0;
+    g.v3 = p3 ? (const View3 *)(base + o_v3) : nullptr;
     g.mat = MatDev{};
     g.pj_wc = PJ_WC_DEFAULT;
     g.pj_ty = PJ_TY_DEFAULT;

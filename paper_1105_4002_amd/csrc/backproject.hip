@@ -20,6 +20,7 @@
 // A view whose footprint exceeds the tile (unusual geometries) takes the
 // generic arithmetic with global loads.
 #include "gather.hpp"
+#include "ray3d.hpp"
 #include "reduce.hpp"
 #include "tvreg_internal.hpp"
 
@@ -125,6 +126,40 @@ __device__ __forceinline__ void gather_cone_tile(const GeomDev &g, const Tile &T
 }
 
 // One block: BP_TX x BP_TY voxel columns, CZ voxels deep, block (bx, by, bz).
+// The 3D parallel beam: the same thread layout, each voxel's rays found by
+// the voxel-driven enumeration of ray3d.hpp (no detector tile staging: a
+// view's footprint on the block is not a row x column rectangle).
+template <typename T, int CZ>
+__device__ __forceinline__ void backproject_block3d(const GeomDev &g, const T *__restrict__ r,
+                                                    T *__restrict__ out, int bx, int by, int bz)
+{
+    const int tid = threadIdx.x;
+    const int ix = bx * BP_TX + (tid % BP_TX);
+    const int iy = by * BP_TY + (tid / BP_TX);
+    const int iz0 = bz * CZ;
+    if (ix >= g.nx || iy >= g.ny)
+        return;
+    double acc[CZ];
+#pragma unroll
+    for (int k = 0; k < CZ; ++k)
+        acc[k] = 0.0;
+    const double X0 = -g.hx + (double)ix, X1 = X0 + 1.0;
+    const double Y0 = -g.hy + (double)iy, Y1 = Y0 + 1.0;
+    const size_t view_stride = (size_t)g.rows * g.cols;
+    for (int v = 0; v < g.nviews; ++v) {
+        const T *rv = r + (size_t)v * view_stride;
+        const double dnv = g.dnorm[v];
+        gather3d_visit<CZ>(g, v, X0, X1, Y0, Y1, iz0, [&](int k, int row, int col, double len) {
+            acc[k] += len * ((double)rv[(size_t)row * g.cols + col] * dnv);
+        });
+    }
+    const size_t plane = (size_t)g.nx * g.ny;
+#pragma unroll
+    for (int k = 0; k < CZ; ++k)
+        if (iz0 + k < g.nz)
+            out[(size_t)(iz0 + k) * plane + (size_t)iy * g.nx + ix] = (T)acc[k];
+}
+
 template <typename T, bool CONE, int CZ>
 __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__restrict__ r,
                                                   T *__restrict__ out, int bx, int by, int bz,
@@ -237,7 +272,10 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_kernel(GeomDev g,
     const int q = nb / N_XCD, rem = nb % N_XCD, k = p % N_XCD;
     const int L = k * q + min(k, rem) + p / N_XCD;
     const int gx = (g.nx + BP_TX - 1) / BP_TX, gy = (g.ny + BP_TY - 1) / BP_TY;
-    backproject_block<T, CONE, CZ>(g, r, out, L % gx, (L / gx) % gy, L / (gx * gy), tile);
+    if (g.beam3d)  // launch-uniform
+        backproject_block3d<T, CZ>(g, r, out, L % gx, (L / gx) % gy, L / (gx * gy));
+    else
+        backproject_block<T, CONE, CZ>(g, r, out, L % gx, (L / gx) % gy, L / (gx * gy), tile);
 }
 
 // Batched: G = A^T RY for every problem whose gradient is due this round.
@@ -254,7 +292,9 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_grouped(BatchProblem<T
     constexpr int BP_CZ = BP_CZ_DEFAULT;
     const int gx = (P.g.nx + BP_TX - 1) / BP_TX, gy = (P.g.ny + BP_TY - 1) / BP_TY;
     const int bx = local % gx, by = (local / gx) % gy, bz = local / (gx * gy);
-    if (P.g.cone)
+    if (P.g.beam3d)  // block-uniform
+        backproject_block3d<T, BP_CZ>(P.g, P.RY, P.G, bx, by, bz);
+    else if (P.g.cone)
         backproject_block<T, true, BP_CZ>(P.g, P.RY, P.G, bx, by, bz, tile);
     else
         backproject_block<T, false, BP_CZ>(P.g, P.RY, P.G, bx, by, bz, tile);

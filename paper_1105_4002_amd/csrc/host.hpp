@@ -14,6 +14,7 @@
 struct tvreg_geometry {
     tvreg_geometry_desc desc;
     std::vector<double> angles;
+    std::vector<double> dirs;  // 3D parallel beam: 3 per view
     tvreg_precision prec;
     int device;
     tvr::GeomDev g;

@@ -20,6 +20,7 @@
 // gather's enumeration, rounded once to T.  The product accumulates in
 // double.
 #include "gather.hpp"
+#include "ray3d.hpp"
 #include "reduce.hpp"
 #include "tvreg_internal.hpp"
 
@@ -55,6 +56,11 @@ __global__ __launch_bounds__(CT_TX *CT_TY) void count_voxels_kernel(GeomDev g,
     for (int k = 0; k < CT_CZ; ++k)
         n[k] = 0;
     for (int v = 0; v < g.nviews; ++v) {
+        if (g.beam3d) {  // launch-uniform
+            gather3d_visit<CT_CZ>(g, v, X0, X1, Y0, Y1, iz0,
+                                  [&](int k, int, int, double) { n[k]++; });
+            continue;
+        }
         const GlobalSrc<float, CONE> src{&g, g.col + (size_t)v * g.cols, nullptr, 0.0};
         gather_view_visit<CONE, CT_CZ>(g, src, g.cs[v].x, g.cs[v].y, X0, X1, Y0, Y1, iz0, 0,
                                        g.cols - 1, 0, g.rows - 1,
@@ -104,19 +110,23 @@ __global__ __launch_bounds__(CT_TX *CT_TY) void fill_voxels_kernel(GeomDev g, T 
         last[k] = 0;
     }
     for (int v = 0; v < g.nviews; ++v) {
-        const GlobalSrc<float, CONE> src{&g, g.col + (size_t)v * g.cols, nullptr, 0.0};
         const int64_t vbase = (int64_t)v * g.rows * g.cols;
-        gather_view_visit<CONE, CT_CZ>(
-            g, src, g.cs[v].x, g.cs[v].y, X0, X1, Y0, Y1, iz0, 0, g.cols - 1, 0, g.rows - 1,
-            [&](int k, int row, int col, double len) {
-                if (pos[k] >= end[k])
-                    return;  // never past the lane's slots (the count pass bounds it)
-                const int32_t i = (int32_t)(vbase + (int64_t)row * g.cols + col);
-                val[pos[k]] = (T)(len * ray_dnorm(g, v, row, col));
-                idx[pos[k]] = i;
-                last[k] = i;
-                pos[k] += 64;
-            });
+        auto put = [&](int k, int row, int col, double len) {
+            if (pos[k] >= end[k])
+                return;  // never past the lane's slots (the count pass bounds it)
+            const int32_t i = (int32_t)(vbase + (int64_t)row * g.cols + col);
+            val[pos[k]] = (T)(len * ray_dnorm(g, v, row, col));
+            idx[pos[k]] = i;
+            last[k] = i;
+            pos[k] += 64;
+        };
+        if (g.beam3d) {  // launch-uniform
+            gather3d_visit<CT_CZ>(g, v, X0, X1, Y0, Y1, iz0, put);
+            continue;
+        }
+        const GlobalSrc<float, CONE> src{&g, g.col + (size_t)v * g.cols, nullptr, 0.0};
+        gather_view_visit<CONE, CT_CZ>(g, src, g.cs[v].x, g.cs[v].y, X0, X1, Y0, Y1, iz0, 0,
+                                       g.cols - 1, 0, g.rows - 1, put);
     }
 #pragma unroll
     for (int k = 0; k < CT_CZ; ++k) {

@@ -13,6 +13,7 @@
 // the line search).
 #include <algorithm>
 
+#include "ray3d.hpp"
 #include "raywalk.hpp"
 #include "reduce.hpp"
 #include "tvreg_internal.hpp"
@@ -68,8 +69,14 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
     const int row = (by * TY + (int)threadIdx.y) * RayTile<WC>::rows + (int)threadIdx.x / WC;
     double red[2] = {0.0, 0.0};
     if (col < g.cols && row < g.rows) {
-        const ColEntry ce = g.col[(size_t)v * g.cols + col];
-        const RowEntry re = g.row[row];
+        ColEntry ce;
+        RowEntry re;
+        if (g.beam3d) {  // launch-uniform
+            ray3d_entries(g, v, row, col, ce, re);
+        } else {
+            ce = g.col[(size_t)v * g.cols + col];
+            re = g.row[row];
+        }
         // rays mostly along x read the y-fastest copy when one is given
         const double cv = g.cs[v].x, sv = g.cs[v].y;
         const bool use_t = xt != nullptr && fabs(cv) > fabs(sv);

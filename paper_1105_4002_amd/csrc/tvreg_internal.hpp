@@ -28,6 +28,12 @@ __host__ __device__ __forceinline__ double plane_t(double X, double invD, double
     return fma(X, invD, o);
 }
 
+// One view of the 3D parallel beam: unit direction d, detector axes e_u, e_v
+// and 1/d per component (0 where d has none).
+struct View3 {
+    double dx, dy, dz, ux, uy, uz, vx, vy, vz, idx, idy, idz;
+};
+
 // Optional stored transpose A^T in SELL-64 form (slices of 64 consecutive
 // voxels; entry k of lane l of slice s at off[s] + 64 k + l): values
 // a_ij = length |D_i| as T, ray indices int32.
@@ -49,11 +55,13 @@ struct GeomDev {
     double R, SDD;             // cone only
     double cu0, rv0;           // (cols - 1) / 2, (rows - 1) / 2
     double hx, hy, hz;         // nx / 2, ny / 2, nz / 2
-    const double2 *cs;         // [nviews] (cos theta, sin theta)
+    const double2 *cs;         // [nviews] (cos theta, sin theta); 3D beam: (d_x, d_y)
     const ColEntry *col;       // [nviews * cols]
     const RowEntry *row;       // [rows]
     const double *dnorm;       // |D|: cone [rows * cols], parallel [nviews]
     MatDev mat;                // stored A^T when present
+    int beam3d;                // 3D parallel beam: rays from v3, not from col / row
+    const View3 *v3;           // [nviews] (3D parallel beam only)
     int pj_wc;                 // projector: detector columns of a wave's ray tile (8, 16, 32, 64)
     int pj_ty;                 // projector: ray tiles (waves) per block, stacked along rows (1, 2, 4, 8)
     int bp_cz;                 // on-the-fly backprojector: voxels per thread along z (4, 8, 16)

@@ -70,6 +70,21 @@ def test_create_geometry_rejects_non_finite_angle(tv):
     assert tv.lib().tvreg_create_geometry(ctypes.byref(d), tv.F32, ctypes.byref(h)) == tv.EINVAL
 
 
+@pytest.mark.parametrize("dirs", [None, [0.0, 0.0, 1.0, 0.0, 0.0, 0.0],
+                                  [0.0, 0.0, 1.0, math.nan, 0.0, 1.0],
+                                  [0.0, 0.0, 1.0, math.inf, 1.0, 0.0]])
+def test_create_geometry_rejects_bad_3d_directions(tv, dirs):
+    d, _keep = _desc(tv, beam=tv.PARALLEL_3D)
+    if dirs is not None:
+        arr = (ctypes.c_double * len(dirs))(*dirs)
+        d.view_dirs = ctypes.cast(arr, tv._c_dp)
+    h = ctypes.c_void_p()
+    assert tv.lib().tvreg_create_geometry(ctypes.byref(d), tv.F32, ctypes.byref(h)) == tv.EINVAL
+    assert not h.value
+    assert "direction" in tv.lib().tvreg_last_error().decode() or "view_dirs" in \
+        tv.lib().tvreg_last_error().decode()
+
+
 def test_null_arguments_rejected(tv):
     L = tv.lib()
     assert L.tvreg_project(None, None, None, None) == tv.EINVAL
