@@ -134,6 +134,58 @@ def grad_eval_loop(tv, torch, G, b, x, w, n: int = 100, runs: int = 5) -> dict:
             "ms_per_eval": round(1e3 / rates[len(rates) // 2], 4)}
 
 
+def paper_leg(tv, synth, torch, dev, eps: float = 1e-8, max_iter: int = 20000) -> dict:
+    """The paper's experiment (Sec. IV): 64^3, parallel beam with view
+    directions over the unit sphere, 55 (many-view) and 19 (few-view) views of
+    91^2 pixels, 1 % noise, alpha = 1e-2 (ellipsoids stand in for FORBILD).
+    FP64 with the stored A^T and tuned shapes.  GP, GPBB and UPN run to the
+    paper's stop test |G|/N <= eps (eq. 10, stop_mode 1); phi* is UPN at
+    eps / 100, as in the paper.  Reported per method: iterations, seconds,
+    status, and the relative gap (phi_k - phi*) / phi* after 10, 100, 500,
+    1000, 2000 iterations and the first k where it falls below 1e-6."""
+    out = {}
+    for views in (55, 19):
+        w = synth.cfg_paper(views)
+        G = tv.Geometry(w.geom, tv.F64)
+        xt = torch.from_numpy(w.phantom()).to(dev)
+        ax = tv.project(G, xt)
+        sigma = w.eta * torch.linalg.vector_norm(ax).item() / math.sqrt(ax.numel())
+        b = (ax + sigma * torch.from_numpy(w.unit_noise()).to(dev)).float().double().contiguous()
+        del ax
+        G.attach_matrix()
+        G.autotune(reps=5)
+        common = dict(alpha=w.alpha, tau=w.tau, stop_mode=1)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        _, istar, _ = tv.solve(G, b, method=tv.UPN, eps=eps / 100, max_iter=10 * max_iter,
+                               **common)
+        torch.cuda.synchronize()
+        phi_star = istar["phi"]
+        case = {"views": views, "rays": w.geom.n_rays, "voxels": w.geom.n_voxels,
+                "phi_star": phi_star, "phi_star_iters": istar["iters"],
+                "phi_star_status": istar["stop_reason"],
+                "phi_star_seconds": round(time.perf_counter() - s0, 3)}
+        for meth, name in ((tv.UPN, "upn"), (tv.GPBB, "gpbb"), (tv.GP, "gp")):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            _, info, h = tv.solve(G, b, method=meth, eps=eps, max_iter=max_iter,
+                                  hist_len=max_iter, **common)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - s0
+            gap = [(p - phi_star) / phi_star for p in h["phi"]]
+            first = next((k + 1 for k, v in enumerate(gap) if v <= 1e-6), None)
+            case[name] = {"iters": info["iters"], "status": info["stop_reason"],
+                          "seconds": round(dt, 3), "grad_evals": info["grad_evals"],
+                          "func_evals": info["func_evals"],
+                          "gap_at": {k: gap[k - 1] for k in (10, 100, 500, 1000, 2000)
+                                     if k <= len(gap)},
+                          "final_gap": gap[-1] if gap else None,
+                          "first_iter_gap_below_1e-6": first}
+        out[f"views{views}"] = case
+        del G
+    return out
+
+
 def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool,
               stored: bool = False):
     """The 32-problem batch (uneven sizes, views and alphas), FP32 UPN to tol:
@@ -239,6 +291,8 @@ def main() -> int:
     ap.add_argument("--methods", action="store_true",
                     help="also time GP and GPBB (FP32 and FP64) to tolerance")
     ap.add_argument("--methods-max-iter", type=int, default=3000)
+    ap.add_argument("--paper", action="store_true",
+                    help="also run the paper's 64^3 experiment (55 and 19 sphere views)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -449,6 +503,10 @@ def main() -> int:
                 del ws
                 if label == "f64" and stored:
                     G.detach_matrix()
+    if args.paper:
+        log("the paper's experiment: 64^3, 55 and 19 views over the sphere, GP/GPBB/UPN FP64")
+        result["paper_experiment"] = paper_leg(tv, synth, torch, dev)
+        log(f"  {result['paper_experiment']}")
     if args.gp64_iters > 0:
         log(f"GP FP64 for up to {args.gp64_iters} iterations")
         ws = tv.solve_workspace(G64, tv.GP)
