@@ -26,6 +26,10 @@ solve (GP)        eq. 6 + Alg. 2 (BT)                     alpha = 0 vs scipy.opt
 solve (GPBB)      Alg. 1                                  all three methods reach the same minimiser;
 solve (UPN)       Alg. 3 + eq. 9                          invariants (L monotone, mu in [0, mu_bar]);
                                                           mu := L reduces UPN to GP bit for bit
+solve (NESTEROV)  Nesterov's method, given mu and L       numpy textbook constant-momentum
+                  (Sec. III-B, rate of eq. 8)             projected scheme on a dense problem
+solve, box Q      P_Q = clip to [lower, upper] (Sec. III) scipy.optimize.lsq_linear (bounded LS);
+                                                          unbounded box = numpy lstsq
 tv_hessvec        derivative of the TV gradient (eq. 2)   central differences of tv's gradient;
                                                           symmetry; quadratic regime = Laplacian
 unrolled          K steps of Alg. 3 and the reverse-mode   K = 1 closed form; central differences
@@ -45,7 +49,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "tvreg_oracle.c")
 
-GP, GPBB, UPN = 0, 1, 2
+GP, GPBB, UPN, NESTEROV = 0, 1, 2, 3
 CONVERGED, NOTCONV, STALL = 0, 1, 2
 
 
@@ -77,7 +81,8 @@ class _Params(ctypes.Structure):
                 ("rho_L", ctypes.c_double), ("gpbb_K", ctypes.c_int32),
                 ("gpbb_sigma", ctypes.c_double), ("gpbb_beta0", ctypes.c_double),
                 ("max_trials", ctypes.c_int32), ("max_squarings", ctypes.c_int32),
-                ("force_mu", ctypes.c_int32), ("bt_form", ctypes.c_int32)]
+                ("force_mu", ctypes.c_int32), ("bt_form", ctypes.c_int32),
+                ("lower", ctypes.c_double), ("upper", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -114,6 +119,9 @@ def lib():
         L.og_phi_grad.restype = ctypes.c_double
         L.og_gradmap_norm.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double]
         L.og_gradmap_norm.restype = ctypes.c_double
+        L.og_gradmap_norm_box.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double]
+        L.og_gradmap_norm_box.restype = ctypes.c_double
         L.og_slab_length.argtypes = [dp, dp, dp, dp]
         L.og_slab_length.restype = ctypes.c_double
         L.og_ray_endpoints.argtypes = [gp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp]
@@ -267,17 +275,20 @@ def phi_grad(g, b, alpha: float, tau: float, x):
     return float(f), gr
 
 
-def gradmap_norm(x, grad, nu: float) -> float:
+def gradmap_norm(x, grad, nu: float, lower: float = 0.0, upper: float = float("inf")) -> float:
     x = _f64(x)
     grad = _f64(grad)
-    return float(lib().og_gradmap_norm(x.size, _dp(x), _dp(grad), nu))
+    if lower == 0.0 and upper == float("inf"):
+        return float(lib().og_gradmap_norm(x.size, _dp(x), _dp(grad), nu))
+    return float(lib().og_gradmap_norm_box(x.size, _dp(x), _dp(grad), nu, lower, upper))
 
 
 def default_params(method: int, alpha: float, tau: float = 1e-4, eps: float = 1e-6,
                    max_iter: int = 10000, **kw) -> dict:
     p = dict(method=method, alpha=alpha, tau=tau, eps=eps, stop_mode=0, max_iter=max_iter,
              L_bar=1.0, mu_bar=0.0, rho_L=2.0, gpbb_K=2, gpbb_sigma=0.1, gpbb_beta0=0.95,
-             max_trials=60, max_squarings=30, force_mu=0, bt_form=0)
+             max_trials=60, max_squarings=30, force_mu=0, bt_form=0, lower=0.0,
+             upper=float("inf"))
     p.update(kw)
     return p
 

@@ -611,15 +611,25 @@ double og_phi_grad(const og_geom *g, const double *b, double alpha, double tau,
 /* P_Q for Q = nonnegative orthant (Sec. IV-A) */
 static double pq(double v) { return v > 0.0 ? v : 0.0; }
 
+/* P_Q for a box Q = [lo, hi]^N (Sec. III: any feasible set with an easy
+   projection); equals pq for lo = 0, hi = +inf */
+static double pq_box(double v, double lo, double hi) { return v > lo ? (v < hi ? v : hi) : lo; }
+
 /* |G_nu(x)|_2 with G_nu(x) = nu (x - P_Q(x - grad/nu))  (eq. 10) */
-double og_gradmap_norm(int64_t n, const double *x, const double *grad, double nu)
+double og_gradmap_norm_box(int64_t n, const double *x, const double *grad, double nu, double lo,
+                           double hi)
 {
     double s = 0.0;
     for (int64_t j = 0; j < n; ++j) {
-        double gj = nu * (x[j] - pq(x[j] - grad[j] / nu));
+        double gj = nu * (x[j] - pq_box(x[j] - grad[j] / nu, lo, hi));
         s += gj * gj;
     }
     return sqrt(s);
+}
+
+double og_gradmap_norm(int64_t n, const double *x, const double *grad, double nu)
+{
+    return og_gradmap_norm_box(n, x, grad, nu, 0.0, INFINITY);
 }
 
 static double dist2(int64_t n, const double *a, const double *b)
@@ -679,7 +689,8 @@ static double op_bregman(const og_op *op, const og_params *p, const double *x, c
  * f(x) > f(y) + grad^T (x - y) + L~/2 |x - y|^2, multiply L~ by rho_L and
  * recompute x.  Returns 0 on acceptance, -1 when max_trials growths did not
  * satisfy the test (x then holds the last trial).  bt_form = 1 evaluates the
- * same inequality as Bregman_f(x, y) > L~/2 |x - y|^2.
+ * same inequality as Bregman_f(x, y) > L~/2 |x - y|^2.  Nesterov's method
+ * with a known L (Sec. III-B) takes the step 1/L without the test.
  */
 static int op_bt(const og_op *op, const double *b, const og_params *p, const double *y,
                  double fy, const double *gy, double L_start, double *x, double *fx_out,
@@ -688,11 +699,13 @@ static int op_bt(const og_op *op, const double *b, const og_params *p, const dou
     double L = L_start;
     for (int32_t trial = 0;; ++trial) {
         for (int64_t j = 0; j < op->N; ++j)
-            x[j] = pq(y[j] - gy[j] / L);
+            x[j] = pq_box(y[j] - gy[j] / L, p->lower, p->upper);
         double fx = op_f(op, b, p->alpha, p->tau, x, tmp_m);
         info->func_evals++;
         int reject;
-        if (p->bt_form == 1) {
+        if (p->method == OG_NESTEROV) {
+            reject = 0;
+        } else if (p->bt_form == 1) {
             double br = op_bregman(op, p, x, y, tmp_n, tmp_m);
             reject = br > 0.5 * L * dist2(op->N, x, y);
         } else {
@@ -722,7 +735,9 @@ static int stop_now(const og_params *p, double gm, double gm0, int64_t N)
 
 /*
  * GP (eq. 6) with step 1/L_k from BT warm-started at L_{k-1}, and UPN
- * (Alg. 3).  GP is UPN with beta_k = 0.  The stop test (Sec. III-D) uses the
+ * (Alg. 3).  GP is UPN with beta_k = 0.  Nesterov's method for given mu and
+ * L (Sec. III-B, rate of eq. 8) is UPN with L_k = L_bar (no line-search
+ * test) and mu_k = mu_bar (no eq. 9 estimate).  The stop test (Sec. III-D) uses the
  * gradient map at the point whose gradient was just evaluated (x^(k) for GP,
  * y^(k) for UPN) with nu = L_k, which equals L_k (z - x^(k+1)).
  */
@@ -731,7 +746,8 @@ static int32_t solve_gp_upn(const og_op *op, const double *b, const og_params *p
                             int32_t hlen)
 {
     int64_t N = op->N, m = op->m;
-    int upn = p->method == OG_UPN;
+    int nest = p->method == OG_NESTEROV;
+    int upn = p->method == OG_UPN || nest;
     double *xk = (double *)malloc(sizeof(double) * N);   /* x^(k) */
     double *xn = (double *)malloc(sizeof(double) * N);   /* x^(k+1) */
     double *y = (double *)malloc(sizeof(double) * N);    /* y^(k) */
@@ -756,6 +772,8 @@ static int32_t solve_gp_upn(const og_op *op, const double *b, const og_params *p
     record(hgm, hlen, 0, 1.0);
     record(hL, hlen, 0, L);
     double mu = p->mu_bar > 0.0 ? p->mu_bar : 0.25 * L;
+    if (nest)
+        mu = p->mu_bar > 0.0 ? p->mu_bar : 0.0;
     if (p->force_mu == 1)
         mu = L;
     else if (p->force_mu == 2)
@@ -801,7 +819,9 @@ static int32_t solve_gp_upn(const og_op *op, const double *b, const og_params *p
         if (upn) {
             /* eq. 9 between x^(k) and y^(k); skipped where they coincide */
             double nd = dist2(N, xk, y);
-            if (p->force_mu == 1) {
+            if (nest) {
+                /* mu and L are given */
+            } else if (p->force_mu == 1) {
                 mu = L;
             } else if (p->force_mu == 2) {
                 mu = 0.0;
@@ -897,7 +917,7 @@ static int32_t solve_gpbb(const og_op *op, const double *b, const og_params *p, 
             if (sy > 0.0 && isfinite(sy) && isfinite(ss / sy) && ss > 0.0)
                 theta = ss / sy;
         }
-        double gm = og_gradmap_norm(N, xk, gk, 1.0 / theta);
+        double gm = og_gradmap_norm_box(N, xk, gk, 1.0 / theta, p->lower, p->upper);
         if (k == 0) {
             gm0 = gm;
             info->gm0 = gm0;
@@ -919,7 +939,7 @@ static int32_t solve_gpbb(const og_op *op, const double *b, const og_params *p, 
         int ok = 0;
         for (int32_t sq = 0; sq <= p->max_squarings; ++sq) {
             for (int64_t j = 0; j < N; ++j)
-                xb[j] = pq(xk[j] - beta * theta * gk[j]);
+                xb[j] = pq_box(xk[j] - beta * theta * gk[j], p->lower, p->upper);
             fb = op_f(op, b, p->alpha, p->tau, xb, tm);
             info->func_evals++;
             double gd = 0.0;
@@ -967,7 +987,7 @@ static int32_t solve_op(const og_op *op, const double *b, const og_params *p, do
 {
     memset(info, 0, sizeof(*info));
     for (int64_t j = 0; j < op->N; ++j)
-        x[j] = pq(x[j]); /* start from a feasible point */
+        x[j] = pq_box(x[j], p->lower, p->upper); /* start from a feasible point */
     if (p->method == OG_GPBB)
         return solve_gpbb(op, b, p, x, info, hphi, hgm, hL, hlen);
     return solve_gp_upn(op, b, p, x, info, hphi, hgm, hL, hmu, hlen);

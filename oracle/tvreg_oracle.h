@@ -32,7 +32,7 @@ typedef struct {
     const double *dirs;     /* beam 2: n_views view directions (x, y, z), any length */
 } og_geom;
 
-enum { OG_GP = 0, OG_GPBB = 1, OG_UPN = 2 };
+enum { OG_GP = 0, OG_GPBB = 1, OG_UPN = 2, OG_NESTEROV = 3 };
 enum { OG_CONVERGED = 0, OG_NOTCONV = 1, OG_STALL = 2 };
 
 typedef struct {
@@ -52,6 +52,8 @@ typedef struct {
                                2 mu_0 := L_0 then mu_k := 0 */
     int32_t bt_form;        /* 0: tests as printed (Alg. 2, eq. 9);
                                1: same inequality via the Bregman distance of f */
+    double lower, upper;    /* Q = [lower, upper]^N (0, +inf: the nonnegative orthant);
+                               the unrolled form always uses the orthant */
 } og_params;
 
 typedef struct {
@@ -84,6 +86,8 @@ double og_phi(const og_geom *g, const double *b, double alpha, double tau, const
 double og_phi_grad(const og_geom *g, const double *b, double alpha, double tau,
                    const double *x, double *grad);
 double og_gradmap_norm(int64_t n, const double *x, const double *grad, double nu);
+double og_gradmap_norm_box(int64_t n, const double *x, const double *grad, double nu, double lo,
+                           double hi);
 
 /* solvers: GP (eq. 6), GPBB (Alg. 1), UPN (Alg. 3), all with the stop test of Sec. III-D */
 int32_t og_solve(const og_geom *g, const double *b, const og_params *p, double *x,
