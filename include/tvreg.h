@@ -59,7 +59,12 @@ typedef enum {
 
 typedef enum { TVREG_PARALLEL = 0, TVREG_CONE = 1, TVREG_PARALLEL_3D = 2 } tvreg_beam;
 typedef enum { TVREG_F32_RED64 = 0, TVREG_F64 = 1 } tvreg_precision;
-typedef enum { TVREG_GP = 0, TVREG_GPBB = 1, TVREG_UPN = 2 } tvreg_method;
+/* TVREG_NESTEROV: Nesterov's method for given mu and L (Sec. III-B, the rate
+   of eq. 8): UPN's recursion with L_k = L_bar (no line search) and
+   mu_k = mu_bar (no eq. 9 estimate); convergent when L_bar is at least the
+   gradient's Lipschitz constant and mu_bar at most the strong-convexity
+   parameter. */
+typedef enum { TVREG_GP = 0, TVREG_GPBB = 1, TVREG_UPN = 2, TVREG_NESTEROV = 3 } tvreg_method;
 
 /* Scan geometry (all lengths in voxel units, volume centred at the origin). */
 typedef struct {
@@ -218,8 +223,10 @@ typedef struct {
     double eps;              /* stop tolerance */
     int32_t stop_mode;       /* 0: |G|/|G_0| <= eps;  1: |G|/N <= eps (as printed) */
     int32_t max_iter;        /* outer iterations (BT or GPBB steps) */
-    double L_bar;            /* initial Lipschitz estimate (Alg. 2/3 input), > 0 */
-    double mu_bar;           /* UPN initial mu; <= 0 selects L_0 / 4 */
+    double L_bar;            /* initial Lipschitz estimate (Alg. 2/3 input), > 0;
+                                NESTEROV: the given L */
+    double mu_bar;           /* UPN initial mu; <= 0 selects L_0 / 4;
+                                NESTEROV: the given mu, in [0, L_bar] */
     double rho_L;            /* BT growth factor, > 1 */
     int32_t gpbb_K;          /* GPBB nonmonotone memory, 0..16 */
     double gpbb_sigma;       /* GPBB sufficient-decrease weight */
@@ -229,6 +236,8 @@ typedef struct {
     double *hist_gm;         /* each accepted point, |G|/|G_0| of each iteration, */
     double *hist_L;          /* and the step's L (1/theta for GPBB) */
     int32_t hist_len;
+    int32_t use_box;         /* 0: Q = {x >= 0} (Sec. IV-A); 1: Q = [lower, upper]^N */
+    double lower, upper;     /* use_box: lower < upper, either may be infinite */
 } tvreg_solve_params;
 
 typedef struct {
@@ -246,9 +255,11 @@ typedef struct {
 size_t tvreg_solve_workspace_bytes(const tvreg_geometry *geom, tvreg_method method);
 
 /*
- * Solves min_{x >= 0} phi(x) with GP (eq. 6, step 1/L_k from BT warm-started
- * at L_{k-1}), GPBB (Alg. 1) or UPN (Alg. 3).  x_inout_dev holds x_0 on entry
- * (negative entries are clipped) and the last accepted iterate on return.
+ * Solves min_{x in Q} phi(x) with GP (eq. 6, step 1/L_k from BT warm-started
+ * at L_{k-1}), GPBB (Alg. 1), UPN (Alg. 3) or Nesterov's method for given mu
+ * and L; Q is the nonnegative orthant or, with use_box, [lower, upper]^N
+ * (P_Q a clip).  x_inout_dev holds x_0 on entry (projected onto Q) and the
+ * last accepted iterate on return.
  * b_dev: m values of T.  The line-search decisions and the mu estimate are
  * evaluated in the rearranged form Bregman_f(x, y) vs L/2 |x - y|^2 (the
  * same inequality as Alg. 2 / eq. 9 without subtracting two objective

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libtvreg.so")
 
 PARALLEL, CONE, PARALLEL_3D = 0, 1, 2
 F32, F64 = 0, 1
-GP, GPBB, UPN = 0, 1, 2
+GP, GPBB, UPN, NESTEROV = 0, 1, 2, 3
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, ESTALL = 0, -1, -2, -3, 1, 2
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -45,7 +45,8 @@ class _SolveParams(ctypes.Structure):
                 ("gpbb_K", ctypes.c_int32), ("gpbb_sigma", ctypes.c_double),
                 ("gpbb_beta0", ctypes.c_double), ("max_trials", ctypes.c_int32),
                 ("hist_phi", _c_dp), ("hist_gm", _c_dp), ("hist_L", _c_dp),
-                ("hist_len", ctypes.c_int32)]
+                ("hist_len", ctypes.c_int32), ("use_box", ctypes.c_int32),
+                ("lower", ctypes.c_double), ("upper", ctypes.c_double)]
 
 
 class _Tuning(ctypes.Structure):
@@ -383,8 +384,10 @@ def solve(geom: Geometry, b: torch.Tensor, method: int = UPN, alpha: float = 1e-
           stop_mode: int = 0, max_iter: int = 10000, L_bar: float = 1.0, mu_bar: float = 0.0,
           rho_L: float = 2.0, gpbb_K: int = 2, gpbb_sigma: float = 0.1,
           gpbb_beta0: float = 0.95, max_trials: int = 60, hist_len: int = 0,
-          workspace: Optional[torch.Tensor] = None):
-    """Runs GP / GPBB / UPN (tvreg_solve).  Returns (x, info dict, history dict)."""
+          workspace: Optional[torch.Tensor] = None, lower: float = 0.0,
+          upper: float = float("inf")):
+    """Runs GP / GPBB / UPN / Nesterov (tvreg_solve) over Q = [lower, upper]^N
+    (default: the nonnegative orthant).  Returns (x, info dict, history dict)."""
     x = (torch.zeros(geom.vol_shape, dtype=geom.dtype, device=b.device) if x0 is None
          else x0.detach().clone().contiguous())
     ws = workspace if workspace is not None else solve_workspace(geom, method, b.device)
@@ -395,7 +398,8 @@ def solve(geom: Geometry, b: torch.Tensor, method: int = UPN, alpha: float = 1e-
                      float(gpbb_sigma), float(gpbb_beta0), int(max_trials),
                      ctypes.cast(hists[0], _c_dp) if hl else None,
                      ctypes.cast(hists[1], _c_dp) if hl else None,
-                     ctypes.cast(hists[2], _c_dp) if hl else None, hl)
+                     ctypes.cast(hists[2], _c_dp) if hl else None, hl,
+                     *_box_fields(lower, upper))
     info = _SolveInfo()
     _check(_lib.tvreg_solve(geom.handle, _ptr(b, geom.dtype, geom.m, "b"), ctypes.byref(p),
                             _ptr(x, geom.dtype, geom.N, "x"), ctypes.c_void_p(ws.data_ptr()),
@@ -404,6 +408,13 @@ def solve(geom: Geometry, b: torch.Tensor, method: int = UPN, alpha: float = 1e-
     n = min(hl, out["iters"])
     hist = {"phi": list(hists[0])[:n], "gm": list(hists[1])[:n], "L": list(hists[2])[:n]}
     return x, out, hist
+
+
+def _box_fields(lower: float, upper: float):
+    """(use_box, lower, upper) of tvreg_solve_params: the orthant unless a
+    box other than [0, inf) is asked for."""
+    lo, hi = float(lower), float(upper)
+    return (0, 0.0, 0.0) if (lo == 0.0 and hi == float("inf")) else (1, lo, hi)
 
 
 def _handles(geoms):
@@ -418,7 +429,8 @@ def solve_batched_workspace(geoms, device="cuda") -> torch.Tensor:
 
 
 _BATCH_DEFAULTS = dict(method=UPN, alpha=1e-2, tau=1e-4, eps=1e-6, stop_mode=0, max_iter=10000,
-                       L_bar=1.0, mu_bar=0.0, rho_L=2.0, max_trials=60)
+                       L_bar=1.0, mu_bar=0.0, rho_L=2.0, max_trials=60, lower=0.0,
+                       upper=float("inf"))
 
 
 def solve_batched(geoms, bs, params, x0s=None, poll_rounds: int = 8,
@@ -426,8 +438,8 @@ def solve_batched(geoms, bs, params, x0s=None, poll_rounds: int = 8,
     """Solves len(geoms) GP / UPN problems together (tvreg_solve_batched).
 
     params: one dict per problem with any of the keys method, alpha, tau,
-    eps, stop_mode, max_iter, L_bar, mu_bar, rho_L, max_trials (defaults as
-    in solve()).  Returns (list of x, list of info dicts, batch status)."""
+    eps, stop_mode, max_iter, L_bar, mu_bar, rho_L, max_trials, lower, upper
+    (defaults as in solve()).  GP, UPN or Nesterov.  Returns (list of x, list of info dicts, batch status)."""
     n = len(geoms)
     if not (len(bs) == n and len(params) == n):
         raise ValueError("geoms, bs and params must have one entry per problem")
@@ -449,7 +461,8 @@ def solve_batched(geoms, bs, params, x0s=None, poll_rounds: int = 8,
         cp[i] = _SolveParams(int(q["method"]), float(q["alpha"]), float(q["tau"]),
                              float(q["eps"]), int(q["stop_mode"]), int(q["max_iter"]),
                              float(q["L_bar"]), float(q["mu_bar"]), float(q["rho_L"]), 2, 0.1,
-                             0.95, int(q["max_trials"]), None, None, None, 0)
+                             0.95, int(q["max_trials"]), None, None, None, 0,
+                             *_box_fields(q["lower"], q["upper"]))
     bp = (ctypes.c_void_p * n)(*[_ptr(bs[i], g.dtype, g.m, f"b[{i}]").value
                                   for i, g in enumerate(geoms)])
     xp = (ctypes.c_void_p * n)(*[_ptr(xs[i], g.dtype, g.N, f"x[{i}]").value

@@ -39,7 +39,8 @@ void tvr::clear_error() { g_err.clear(); }
 
 tvreg_status tvr::check_solve_params(const tvreg_solve_params *p)
 {
-    if (p->method != TVREG_GP && p->method != TVREG_GPBB && p->method != TVREG_UPN)
+    if (p->method != TVREG_GP && p->method != TVREG_GPBB && p->method != TVREG_UPN &&
+        p->method != TVREG_NESTEROV)
         return fail(TVREG_EINVAL, "unknown method %d", (int)p->method);
     if (!(p->tau > 0) || !isfinite(p->tau) || !(p->alpha >= 0) || !isfinite(p->alpha))
         return fail(TVREG_EINVAL, "tau must be > 0 and alpha >= 0");
@@ -55,7 +56,19 @@ tvreg_status tvr::check_solve_params(const tvreg_solve_params *p)
         return fail(TVREG_EINVAL, "GPBB needs 0 <= K <= 16, 0 < beta0 < 1, sigma >= 0");
     if (p->hist_len < 0)
         return fail(TVREG_EINVAL, "hist_len < 0");
+    if (p->method == TVREG_NESTEROV &&
+        (!isfinite(p->L_bar) || !(p->mu_bar >= 0) || !(p->mu_bar <= p->L_bar)))
+        return fail(TVREG_EINVAL, "Nesterov's method needs a finite L_bar and 0 <= mu_bar <= L_bar");
+    if (p->use_box != 0 && p->use_box != 1)
+        return fail(TVREG_EINVAL, "use_box must be 0 or 1");
+    if (p->use_box && !(p->lower < p->upper))
+        return fail(TVREG_EINVAL, "the box needs lower < upper (got %g, %g)", p->lower, p->upper);
     return TVREG_OK;
+}
+
+tvr::Box tvr::box_of(const tvreg_solve_params *p)
+{
+    return p->use_box ? Box{p->lower, p->upper} : ORTHANT;
 }
 
 extern "C" const char *tvreg_last_error(void) { return g_err.c_str(); }
@@ -594,8 +607,8 @@ struct Solver {
     {
         int nb = 0;
         TVR_HIP(run.timed(TVREG_KERNEL_TRIAL, [&] {
-            return launch_trial<T>(nx, ny, nz, p->tau, z, g, step, gm_step, xb, run.part,
-                                   run.pstride, run.st, &nb);
+            return launch_trial<T>(nx, ny, nz, p->tau, z, g, step, gm_step, box_for<T>(p), xb,
+                                   run.part, run.pstride, run.st, &nb);
         }));
         run.add(S_XD2, nb);
         run.add(S_GD, nb);
@@ -606,13 +619,15 @@ struct Solver {
         return TVREG_OK;
     }
 
-    // GP (beta = 0) and UPN.
+    // GP (beta = 0), UPN, and Nesterov's method for given mu and L (UPN with
+    // L and mu held: no line-search test, no eq. 9 estimate).
     tvreg_status gp_upn(T *x_io, tvreg_solve_info *info)
     {
-        const bool upn = p->method == TVREG_UPN;
+        const bool nest = p->method == TVREG_NESTEROV;
+        const bool upn = p->method == TVREG_UPN || nest;
         T *X = vN[0], *XB = vN[1], *Ybuf = vN[2], *Gv = vN[3];
         T *RX = vM[0], *RXB = vM[1], *RYbuf = vM[2];
-        TVR_HIP(launch_clip<T>(N, x_io, X, run.st));
+        TVR_HIP(launch_clip<T>(N, x_io, X, box_for<T>(p), run.st));
         TVR_TRY(project(X, RX, nullptr));
         T *Y = X, *RY = RX;
         TVR_TRY(gradient(Y, RY, nullptr, Gv));
@@ -629,7 +644,7 @@ struct Solver {
                 xd2 = run.hs[S_XD2];
                 const double lhs = 0.5 * run.hs[S_RD2] + p->alpha * run.hs[S_BRB];
                 phi_xb = 0.5 * run.hs[S_R2] + p->alpha * run.hs[S_TVB];
-                if (!(lhs > 0.5 * L * xd2))
+                if (nest || !(lhs > 0.5 * L * xd2))
                     return TVREG_OK;
                 if (t + 1 < p->max_trials)
                     L *= p->rho_L;
@@ -643,7 +658,7 @@ struct Solver {
         double gm = gm0;
         info->iters = 1;
         info->L = L;
-        double mu = p->mu_bar > 0 ? p->mu_bar : 0.25 * L;
+        double mu = nest ? p->mu_bar : (p->mu_bar > 0 ? p->mu_bar : 0.25 * L);
         double theta = sqrt(mu / L);
         double phi_out = phi_xb;
         hist_put(p->hist_phi, p->hist_len, 0, phi_xb);
@@ -693,7 +708,7 @@ struct Solver {
                 if (upn) {
                     // eq. 9 between x^(k) and y^(k), skipped where they coincide
                     const double nd = distinct ? run.hs[S_XY2] : 0.0;
-                    if (nd > 0.0 && have_ry2) {
+                    if (!nest && nd > 0.0 && have_ry2) {
                         const double num = 0.5 * run.hs[S_RY2] + p->alpha * run.hs[S_BRY];
                         mu = fmax(fmin(mu, num / (0.5 * nd)), 0.0);
                     }
@@ -747,7 +762,7 @@ struct Solver {
     {
         T *X = vN[0], *XB = vN[1], *XP = vN[2], *Gv = vN[3], *GP = vN[4];
         T *RX = vM[0], *RXB = vM[1];
-        TVR_HIP(launch_clip<T>(N, x_io, X, run.st));
+        TVR_HIP(launch_clip<T>(N, x_io, X, box_for<T>(p), run.st));
         TVR_TRY(project(X, RX, nullptr));
         TVR_TRY(gradient(X, RX, nullptr, Gv));
         info->grad_evals++;
@@ -910,6 +925,8 @@ template <typename T>
 static tvreg_status solve_impl(const tvreg_geometry *G, const T *b, const tvreg_solve_params *p,
                                T *x, char *ws, tvreg_solve_info *info, hipStream_t st)
 {
+    if (!(box_for<T>(p).lo <= box_for<T>(p).hi))
+        return fail(TVREG_EINVAL, "box narrower than the storage precision");
     const Layout L = solve_layout(G);
     Solver<T> s{};
     s.G = G;

@@ -32,7 +32,8 @@ __device__ void control_step(BatchProblem<T> &P)
     const double lhs = 0.5 * S[S_RD2] + P.alpha * S[S_BRB];
     const double phi_xb = 0.5 * S[S_R2] + P.alpha * S[S_TVB];
     P.ex = 0;
-    if (lhs > 0.5 * P.L * xd2) {  // BT rejects: larger L, same gradient
+    const bool nest = P.method == TVREG_NESTEROV;  // given L: no line-search test
+    if (!nest && lhs > 0.5 * P.L * xd2) {  // BT rejects: larger L, same gradient
         P.trials++;
         P.need_grad = 0;
         if (P.trials >= P.max_trials) {
@@ -59,7 +60,7 @@ __device__ void control_step(BatchProblem<T> &P)
     if (first) {
         P.gm0 = gm;
         P.iters = 1;
-        P.mu = P.mu_bar > 0.0 ? P.mu_bar : 0.25 * P.L;
+        P.mu = nest ? P.mu_bar : (P.mu_bar > 0.0 ? P.mu_bar : 0.25 * P.L);
         P.theta = sqrt(P.mu / P.L);
         P.first = 0;
     } else {
@@ -79,9 +80,9 @@ __device__ void control_step(BatchProblem<T> &P)
         P.need_grad = 0;
         return;
     }
-    if (P.method == TVREG_UPN && !first) {
+    if ((P.method == TVREG_UPN || nest) && !first) {
         const double nd = P.distinct ? S[S_XY2] : 0.0;
-        if (nd > 0.0 && P.have_ry2) {
+        if (!nest && nd > 0.0 && P.have_ry2) {
             const double num = 0.5 * S[S_RY2] + P.alpha * S[S_BRY];
             P.mu = fmax(fmin(P.mu, num / (0.5 * nd)), 0.0);
         }
@@ -290,6 +291,9 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         P.eps = p->eps;
         P.rho = p->rho_L;
         P.mu_bar = p->mu_bar;
+        P.box = box_for<T>(p);
+        if (!(P.box.lo <= P.box.hi))
+            return fail(TVREG_EINVAL, "problem %d: box narrower than the storage precision", i);
         P.L = p->L_bar;
         P.phi = NAN;
         P.method = p->method;
@@ -300,7 +304,7 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         P.first = 1;
         P.grad_evals = 1;
         const GeomDev &g = P.g;
-        TVR_HIP(launch_clip<T>(G->N, (const T *)x_io[i], P.X, st));
+        TVR_HIP(launch_clip<T>(G->N, (const T *)x_io[i], P.X, P.box, st));
         TVR_HIP(launch_transpose_xy<T>(g.nx, g.ny, g.nz, P.X, P.XT, st));
         TVR_HIP(launch_project<T>(g, P.X, P.XT, P.b, P.RX, nullptr, P.part, P.pstride, st,
                                   nullptr));
@@ -385,7 +389,7 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         inf.gm_rel = P.gm0 > 0 ? P.gm / P.gm0 : 0.0;
         inf.gm_abs_over_N = P.gm / (double)P.N;
         inf.L = P.L;
-        inf.mu = P.method == TVREG_UPN ? P.mu : 0.0;
+        inf.mu = P.method == TVREG_UPN || P.method == TVREG_NESTEROV ? P.mu : 0.0;
         inf.stop_reason = P.state == B_CONVERGED ? TVREG_OK
                           : P.state == B_STALL   ? TVREG_ESTALL
                                                  : TVREG_ENOTCONV;

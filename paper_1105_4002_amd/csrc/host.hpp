@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <cmath>
 #include <vector>
 
 #include "tvreg.h"
@@ -31,6 +32,27 @@ void clear_error();
 
 // Argument checks shared by tvreg_solve and tvreg_solve_batched.
 tvreg_status check_solve_params(const tvreg_solve_params *p);
+// The feasible set the parameters select.
+Box box_of(const tvreg_solve_params *p);
+
+// The feasible set in storage type T: for float the bounds are rounded
+// inward, so every stored iterate lies in Q (an empty result, lo > hi, means
+// the box is narrower than one float).
+template <typename T>
+inline Box box_for(const tvreg_solve_params *p)
+{
+    Box b = box_of(p);
+    if (sizeof(T) == sizeof(float)) {
+        float lo = (float)b.lo, hi = (float)b.hi;
+        if ((double)lo < b.lo)
+            lo = nextafterf(lo, __builtin_inff());
+        if ((double)hi > b.hi)
+            hi = nextafterf(hi, -__builtin_inff());
+        b.lo = lo;
+        b.hi = hi;
+    }
+    return b;
+}
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline size_t elem_size(tvreg_precision p) { return p == TVREG_F64 ? 8 : 4; }

@@ -273,12 +273,12 @@ __global__ __launch_bounds__(VX *VY) void tv_grouped(BatchProblem<T> *probs, con
 }
 
 template <typename T>
-__device__ __forceinline__ T pstep(T z, T g, double step)
+__device__ __forceinline__ T pstep(T z, T g, double step, const Box &box)
 {
-    return (T)fmax((double)z - step * (double)g, 0.0);
+    return (T)clip_box((double)z - step * (double)g, box);
 }
 
-// xbar = P_Q(z - step g) (Q = nonnegative orthant) with the sums |xbar - z|^2,
+// xbar = P_Q(z - step g) (Q = [lo, hi]^N, a clip) with the sums |xbar - z|^2,
 // g^T (z - xbar), T(xbar), Bregman_T(xbar, z) and, for gm_step > 0,
 // |z - P_Q(z - gm_step g)|^2 (the GPBB gradient map).  Planes of z and g
 // (with the high-side halo the forward differences need) are staged in LDS
@@ -287,9 +287,9 @@ __device__ __forceinline__ T pstep(T z, T g, double step)
 template <typename T>
 __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
                                             const T *__restrict__ zv, const T *__restrict__ g,
-                                            double step, double gm_step, T *__restrict__ xbar,
-                                            double *__restrict__ partials, int pstride, int bx,
-                                            int by, int bz, int bid)
+                                            double step, double gm_step, const Box box,
+                                            T *__restrict__ xbar, double *__restrict__ partials,
+                                            int pstride, int bx, int by, int bz, int bid)
 {
     __shared__ T zs[2][VY + 1][VX + 1];  // x in [x0, x0 + VX], y in [y0, y0 + VY]
     __shared__ T gs[2][VY + 1][VX + 1];
@@ -324,13 +324,13 @@ __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
             const T(&Z)[VY + 1][VX + 1] = zs[cur];
             const T(&Gc)[VY + 1][VX + 1] = gs[cur];
             const T zj = Z[ty][tx], gj = Gc[ty][tx];
-            const T xj = pstep(zj, gj, step);
+            const T xj = pstep(zj, gj, step, box);
             const T zxp = hx ? Z[ty][tx + 1] : zj;
-            const T xxp = hx ? pstep(zxp, Gc[ty][tx + 1], step) : xj;
+            const T xxp = hx ? pstep(zxp, Gc[ty][tx + 1], step, box) : xj;
             const T zyp = hy ? Z[ty + 1][tx] : zj;
-            const T xyp = hy ? pstep(zyp, Gc[ty + 1][tx], step) : xj;
+            const T xyp = hy ? pstep(zyp, Gc[ty + 1][tx], step, box) : xj;
             const T zzp = hz ? zs[nxt][ty][tx] : zj;
-            const T xzp = hz ? pstep(zzp, gs[nxt][ty][tx], step) : xj;
+            const T xzp = hz ? pstep(zzp, gs[nxt][ty][tx], step, box) : xj;
             xbar[(size_t)ix + sy * iy + sz * z] = xj;
             const double ed = (double)xj - (double)zj;
             red[0] += ed * ed;
@@ -343,7 +343,7 @@ __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
             red[3] += (double)huber_bregman<T>(a0, a1, a2, b0, b1, b2, d0, d1, d2, ct, itau);
             if (gm_step > 0.0) {
                 const double zd = (double)zj;
-                const double p = zd - fmax(zd - gm_step * (double)gj, 0.0);
+                const double p = zd - clip_box(zd - gm_step * (double)gj, box);
                 red[4] += p * p;
             }
         }
@@ -362,12 +362,13 @@ template <typename T>
 __global__ __launch_bounds__(VX *VY) void trial_kernel(int nx, int ny, int nz, double tau,
                                                        const T *__restrict__ zv,
                                                        const T *__restrict__ g, double step,
-                                                       double gm_step, T *__restrict__ xbar,
+                                                       double gm_step, Box box,
+                                                       T *__restrict__ xbar,
                                                        double *__restrict__ partials,
                                                        int pstride)
 {
-    trial_block<T>(nx, ny, nz, tau, zv, g, step, gm_step, xbar, partials, pstride, blockIdx.x,
-                   blockIdx.y, blockIdx.z, block_linear_id());
+    trial_block<T>(nx, ny, nz, tau, zv, g, step, gm_step, box, xbar, partials, pstride,
+                   blockIdx.x, blockIdx.y, blockIdx.z, block_linear_id());
 }
 
 // Batched trial XB = P_Q(Y - G / L) of every running problem.
@@ -382,8 +383,8 @@ __global__ __launch_bounds__(VX *VY) void trial_grouped(BatchProblem<T> *probs, 
     const int local = blockIdx.x - offs[p];
     int bx, by, bz;
     voxel_block_coords(local, P.g.nx, P.g.ny, bx, by, bz);
-    trial_block<T>(P.g.nx, P.g.ny, P.g.nz, P.tau, P.Y, P.G, 1.0 / P.L, 0.0, P.XB, P.part,
-                   P.pstride, bx, by, bz, local);
+    trial_block<T>(P.g.nx, P.g.ny, P.g.nz, P.tau, P.Y, P.G, 1.0 / P.L, 0.0, P.box, P.XB,
+                   P.part, P.pstride, bx, by, bz, local);
 }
 
 // xt[z][x][y] = x[z][y][x] through a 32 x 32 LDS tile per block (both the
@@ -558,13 +559,11 @@ __global__ __launch_bounds__(VB) void bb_dots_kernel(int64_t n, const T *__restr
 
 template <typename T>
 __global__ __launch_bounds__(VB) void clip_kernel(int64_t n, const T *__restrict__ in,
-                                                  T *__restrict__ out)
+                                                  T *__restrict__ out, Box box)
 {
     for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * VB) {
-        const T v = in[i];
-        out[i] = v > T(0) ? v : T(0);
-    }
+         i += (int64_t)gridDim.x * VB)
+        out[i] = (T)clip_box((double)in[i], box);
 }
 
 __global__ __launch_bounds__(VB) void finalize_kernel(SlotList sl, const double *__restrict__ partials,
@@ -631,14 +630,14 @@ hipError_t launch_tv(int nx, int ny, int nz, double tau, double alpha, const T *
 
 template <typename T>
 hipError_t launch_trial(int nx, int ny, int nz, double tau, const T *z, const T *g, double step,
-                        double gm_step, T *xbar, double *partials, int pstride, hipStream_t st,
-                        int *nblocks)
+                        double gm_step, Box box, T *xbar, double *partials, int pstride,
+                        hipStream_t st, int *nblocks)
 {
     const dim3 gr = voxel_grid(nx, ny, nz);
     if (nblocks)
         *nblocks = (int)(gr.x * gr.y * gr.z);
     hipLaunchKernelGGL((trial_kernel<T>), gr, dim3(VX, VY), 0, st, nx, ny, nz, tau, z, g, step,
-                       gm_step, xbar, partials, pstride);
+                       gm_step, box, xbar, partials, pstride);
     return hipGetLastError();
 }
 
@@ -675,9 +674,10 @@ hipError_t launch_transpose_xy(int nx, int ny, int nz, const T *x, T *xt, hipStr
 }
 
 template <typename T>
-hipError_t launch_clip(int64_t n, const T *in, T *out, hipStream_t st)
+hipError_t launch_clip(int64_t n, const T *in, T *out, Box box, hipStream_t st)
 {
-    hipLaunchKernelGGL((clip_kernel<T>), dim3(elementwise_blocks(n)), dim3(VB), 0, st, n, in, out);
+    hipLaunchKernelGGL((clip_kernel<T>), dim3(elementwise_blocks(n)), dim3(VB), 0, st, n, in, out,
+                       box);
     return hipGetLastError();
 }
 
@@ -759,12 +759,12 @@ TVR_INST_GROUPED(double)
     template hipError_t launch_tv<T>(int, int, int, double, double, const T *, const T *,       \
                                      const T *, T *, double *, int, hipStream_t, int *);        \
     template hipError_t launch_trial<T>(int, int, int, double, const T *, const T *, double,     \
-                                        double, T *, double *, int, hipStream_t, int *);        \
+                                        double, Box, T *, double *, int, hipStream_t, int *);   \
     template hipError_t launch_extrapolate<T>(int64_t, double, const T *, const T *, T *,       \
                                               double *, int, hipStream_t, int *);               \
     template hipError_t launch_bb_dots<T>(int64_t, const T *, const T *, const T *, const T *,  \
                                           double *, int, hipStream_t, int *);                   \
-    template hipError_t launch_clip<T>(int64_t, const T *, T *, hipStream_t);                   \
+    template hipError_t launch_clip<T>(int64_t, const T *, T *, Box, hipStream_t);              \
     template hipError_t launch_transpose_xy<T>(int, int, int, const T *, T *, hipStream_t);
 
 TVR_INST(float)

@@ -72,6 +72,18 @@ constexpr int PJ_WC_DEFAULT = 64;
 constexpr int PJ_TY_DEFAULT = 4;
 constexpr int BP_CZ_DEFAULT = 8;
 
+// The feasible set Q = [lo, hi]^N (lo = 0, hi = +inf: the nonnegative
+// orthant) and its projection, a clip evaluated in double.
+struct Box {
+    double lo, hi;
+};
+constexpr Box ORTHANT{0.0, __builtin_inf()};
+
+__host__ __device__ __forceinline__ double clip_box(double v, const Box &b)
+{
+    return v > b.lo ? (v < b.hi ? v : b.hi) : b.lo;
+}
+
 // Double-precision reduction results live in fixed slots; every kernel that
 // reduces writes one partial per block into partials[slot * pstride + block]
 // and finalize_slots() sums each slot in a fixed order.
@@ -126,11 +138,11 @@ hipError_t launch_tv(int nx, int ny, int nz, double tau, double alpha, const T *
                      const T *gin, T *gout, double *partials, int pstride, hipStream_t st,
                      int *nblocks);
 
-// xbar = max(z - step g, 0); slots S_XD2, S_GD, S_TVB, S_BRB and (gm_step > 0) S_GM2.
+// xbar = P_Q(z - step g); slots S_XD2, S_GD, S_TVB, S_BRB and (gm_step > 0) S_GM2.
 template <typename T>
 hipError_t launch_trial(int nx, int ny, int nz, double tau, const T *z, const T *g, double step,
-                        double gm_step, T *xbar, double *partials, int pstride, hipStream_t st,
-                        int *nblocks);
+                        double gm_step, Box box, T *xbar, double *partials, int pstride,
+                        hipStream_t st, int *nblocks);
 
 // y = xn + beta (xn - xo) over n entries; with part != NULL adds sum (y - xn)^2 to S_RY2.
 template <typename T>
@@ -142,9 +154,9 @@ template <typename T>
 hipError_t launch_bb_dots(int64_t n, const T *x, const T *xp, const T *g, const T *gp,
                           double *partials, int pstride, hipStream_t st, int *nblocks);
 
-// out = max(in, 0)
+// out = P_Q(in)
 template <typename T>
-hipError_t launch_clip(int64_t n, const T *in, T *out, hipStream_t st);
+hipError_t launch_clip(int64_t n, const T *in, T *out, Box box, hipStream_t st);
 
 hipError_t launch_finalize(const SlotList &sl, const double *partials, int pstride,
                            hipStream_t st);
@@ -215,6 +227,7 @@ struct BatchProblem {
     double *part;     // per-block partial sums [S_COUNT][pstride]
     double *sum;      // finalised sums [S_COUNT]
     double alpha, tau, eps, rho, mu_bar;
+    Box box;          // Q
     double L, mu, theta, beta, gm0, gm, phi;
     int method, stop_mode, max_iter, max_trials;
     int state, first, need_grad, ex, distinct, have_ry2, ry2_pending, trials;

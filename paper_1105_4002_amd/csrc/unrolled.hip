@@ -187,8 +187,8 @@ struct Unroller {
                 L = L_replay[j];
             for (int t = 0;; ++t) {
                 int nbt = 0, nbp = 0;
-                TVR_HIP(launch_trial<T>(g.nx, g.ny, g.nz, tau, Y, Gv, 1.0 / L, 0.0, XN, part,
-                                        G->pstride, st, &nbt));
+                TVR_HIP(launch_trial<T>(g.nx, g.ny, g.nz, tau, Y, Gv, 1.0 / L, 0.0, ORTHANT, XN,
+                                        part, G->pstride, st, &nbt));
                 TVR_TRY(project(XN, b, RXB, RY, &nbp));
                 if (L_replay)
                     break;
@@ -260,7 +260,7 @@ struct Unroller {
             xs[i + 1] = segN(2 * i);
             TVR_TRY(gradient(ys[i], nullptr, RY, Gv, false));
             TVR_HIP(launch_trial<T>(g.nx, g.ny, g.nz, tau, ys[i], Gv, 1.0 / rec[j].L, 0.0,
-                                    xs[i + 1], part, G->pstride, st, nullptr));
+                                    ORTHANT, xs[i + 1], part, G->pstride, st, nullptr));
             if (j + 1 < e) {
                 ys[i + 1] = segN(2 * i + 1);
                 TVR_TRY(advance_y(j, rec[j].beta, xs[i + 1], xs[i], ys[i + 1]));
