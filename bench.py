@@ -42,18 +42,32 @@ HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 
 # HBM bytes per launch of the stored-A^T product, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE scaled by a 1 GiB copy (profiles/cone256_kernels_hbm_traffic_pmc.md);
-# reported only while the kernel source is the one measured.
+# reported only while the product kernel's source (its block-size constant and
+# the body of spmv_voxels_block) is the one measured.
 MEASURED_TRAFFIC = {"kernel": "backproject", "source": "paper_1105_4002_amd/csrc/matrix.hip",
-                    "sha256_prefix": "84fca6d7b080f00d", "bytes": 12.266e9 + 0.067e9}
+                    "function": "spmv_voxels_block", "sha256_prefix": "dce32311712271e6",
+                    "bytes": 12.266e9 + 0.067e9}
+
+
+def kernel_source(path: str, function: str) -> str:
+    """The block-size constant and the text of `function` (signature to the
+    closing brace at column 0) in a HIP source file."""
+    text = open(path).read()
+    const = next(ln for ln in text.splitlines() if ln.startswith("constexpr int MB"))
+    start = text.index(f"void {function}(")
+    start = text.rindex("template", 0, start)
+    end = text.index("\n}\n", start) + 3
+    return const + "\n" + text[start:end]
 
 
 def measured_traffic(kernel: str, stored: bool):
     import hashlib
     if not stored or kernel != MEASURED_TRAFFIC["kernel"]:
         return None
-    with open(os.path.join(ROOT, MEASURED_TRAFFIC["source"]), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
-    if not sha.startswith(MEASURED_TRAFFIC["sha256_prefix"]):
+    src = kernel_source(os.path.join(ROOT, MEASURED_TRAFFIC["source"]),
+                        MEASURED_TRAFFIC["function"])
+    sha = hashlib.sha256(src.encode()).hexdigest()
+    if not sha.startswith(MEASURED_TRAFFIC["sha256_prefix"] or "-"):
         return None
     return round(MEASURED_TRAFFIC["bytes"] / 1e9, 3)
 FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed math)
