@@ -250,9 +250,12 @@ def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool
 
 def unrolled_leg(tv, synth, torch, dev, reps: int = 3):
     """The differentiated form: 64^3, cone beam, 30 views, 96 x 96, K = 30
-    unrolled UPN steps, forward + reverse pass in FP32 (checkpoints every 5)."""
+    unrolled UPN steps, forward + reverse pass in FP32 (checkpoints every 5),
+    with the stored A^T and autotuned shapes."""
     w = synth.cfg_unrolled()
     G = tv.Geometry(w.geom, tv.F32)
+    G.attach_matrix()
+    G.autotune(reps=5)
     G64 = tv.Geometry(w.geom, tv.F64)
     xt = torch.from_numpy(w.phantom()).to(dev)
     ax = tv.project(G64, xt)

@@ -7,9 +7,10 @@ from the oracle (its projection of the phantom plus the seeded noise).
   same FP32 values: phi within 1e-6 relative; every gradient element within
   the FP32 rounding of its data part plus a 2e-6 allowance relative to the
   gradient's scale (the FP32 TV stencil, as in the TV test at this size).
-* Ten UPN iterations from x0 = 0: the iterate is feasible, and the objective
-  the solver reports for it (an FP64 sum over its FP32 residual and TV
-  terms) matches the oracle's phi at the returned FP32 iterate within 1e-6.
+* Ten UPN, GPBB and GP iterations from x0 = 0: the iterate is feasible, and
+  the objective the solver reports for it (an FP64 sum over its FP32
+  residual and TV terms) matches the oracle's phi at the returned FP32
+  iterate within 1e-6.
 """
 import numpy as np
 import pytest
@@ -62,10 +63,12 @@ def test_cone256_objective_grad_matches_oracle(scan):
     assert not bad.any(), f"{bad.sum()} gradient entries off, worst {np.max(np.abs(got - g_ref)):.3e}"
 
 
-def test_cone256_upn_iterations_objective_matches_oracle(scan):
+@pytest.mark.parametrize("method", ["upn", "gpbb", "gp"])
+def test_cone256_iterations_objective_matches_oracle(scan, method):
     w, b, G, bd = scan
-    print("cone256: 10 UPN iterations", flush=True)
-    x, info, _ = tv.solve(G, bd, method=tv.UPN, alpha=w.alpha, tau=w.tau, eps=0.0, max_iter=10)
+    m = {"upn": tv.UPN, "gpbb": tv.GPBB, "gp": tv.GP}[method]
+    print(f"cone256: 10 {method} iterations", flush=True)
+    x, info, _ = tv.solve(G, bd, method=m, alpha=w.alpha, tau=w.tau, eps=0.0, max_iter=10)
     assert info["iters"] == 10
     xh = x.cpu().double().numpy()
     assert xh.min() >= 0.0
