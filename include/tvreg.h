@@ -310,9 +310,11 @@ tvreg_status tvreg_solve_batched(int32_t n, const tvreg_geometry *const *geoms,
  * when L_replay != NULL, taken from L_replay[j] with no test; mu_j follows
  * eq. 9 (skipped while x^(j) = y^(j)), theta and beta follow Alg. 3, and
  * xK_dev receives x^(K) (the K-th BT output).  Uses params->alpha, tau,
- * L_bar, mu_bar, rho_L and max_trials.  The tape (device workspace of
- * tvreg_unrolled_workspace_bytes) keeps the step scalars and (x, y) every
- * ckpt_every steps; L_out (host, K entries, may be NULL) receives the L_j.
+ * L_bar, mu_bar, rho_L and max_trials; params->method must be TVREG_UPN and
+ * use_box 0 (Q is the nonnegative orthant), else TVREG_EINVAL.  The tape
+ * (device workspace of tvreg_unrolled_workspace_bytes) keeps the step
+ * scalars and (x, y) every ckpt_every steps; L_out (host, K entries, may be
+ * NULL) receives the L_j.
  * Returns TVREG_ESTALL when a BT search hits max_trials (no gradient then).
  *
  * The reverse pass, given dl/dx^(K) (N values of T, device), writes

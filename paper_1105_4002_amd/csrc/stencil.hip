@@ -158,6 +158,9 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
     }
     PlaneRegs<T, VY + 2, VX + 2> ry;
     PlaneRegs<T, VY + 1, VX + 1> rx;
+    // the gradient being added to, one plane ahead
+    const bool addg = gin != nullptr && gout != nullptr && active;
+    T gin_next = addg && z0 < z1 ? gin[(size_t)ix + sy * iy + sz * z0] : T(0);
     for (int z = z0; z < z1; ++z) {
         const int nxt = cur ^ 1;
         const bool hz = z + 1 < nz;
@@ -168,6 +171,9 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
             if (xref)
                 load_plane(xref, nx, ny, x0, y0, 0, z + 2, rx);
         }
+        const T gin_cur = gin_next;
+        if (addg && z + 1 < z1)
+            gin_next = gin[(size_t)ix + sy * iy + sz * (z + 1)];
         if (active) {
             const T(&Y)[VY + 2][VX + 2] = ys[cur];
             const T(&Yn)[VY + 2][VX + 2] = ys[nxt];
@@ -198,7 +204,7 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
             }
             const size_t j = (size_t)ix + sy * iy + sz * z;
             if (gout)
-                gout[j] = gin ? (T)((double)gin[j] + alpha * (double)gsum)
+                gout[j] = gin ? (T)((double)gin_cur + alpha * (double)gsum)
                               : (T)(alpha * (double)gsum);
             if (partials) {
                 red[0] += (double)huber_c<T>(d2, ct, itau);

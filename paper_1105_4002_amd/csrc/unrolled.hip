@@ -359,6 +359,11 @@ tvreg_status check_unrolled(const tvreg_geometry *G, const tvreg_solve_params *p
         return fail(TVREG_EINVAL, "tau must be > 0 and alpha >= 0");
     if (!(p->L_bar > 0) || !isfinite(p->L_bar) || !(p->rho_L > 1) || p->max_trials < 1)
         return fail(TVREG_EINVAL, "need L_bar > 0, rho_L > 1, max_trials >= 1");
+    // the differentiated form is UPN over the nonnegative orthant
+    if (p->method != TVREG_UPN)
+        return fail(TVREG_EINVAL, "the unrolled form runs UPN (method %d given)", (int)p->method);
+    if (p->use_box)
+        return fail(TVREG_EINVAL, "the unrolled form uses Q = {x >= 0}; use_box must be 0");
     return TVREG_OK;
 }
 

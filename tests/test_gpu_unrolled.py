@@ -270,3 +270,24 @@ def test_unrolled_stall_and_bad_arguments():
         tv.upn_unrolled_bwd(G2, dev(np.zeros(w.proj_shape), tv.F32), tape,
                             torch.zeros(w.vol_shape, device=DEV))
     assert e.value.status == tv.EINVAL
+
+
+def test_unrolled_rejects_other_methods_and_boxes():
+    """The differentiated form is UPN over the orthant: other methods and a
+    box are refused through the C ABI rather than ignored."""
+    import ctypes
+    geom, og, xt, b = small_problem()
+    G = tv.Geometry(geom, tv.F32)
+    bd = dev(b, tv.F32)
+    tape = tv.unrolled_workspace(G, 3, 5)
+    xK = G.empty_volume()
+    for method, box in ((tv.GP, (0, 0.0, 0.0)), (tv.NESTEROV, (0, 0.0, 0.0)),
+                        (tv.UPN, (1, 0.0, 1.0))):
+        p = tv._SolveParams(method, 1e-2, 1e-4, 0.0, 0, 1, 1.0, 0.0, 2.0, 2, 0.1, 0.95, 60,
+                            None, None, None, 0, *box)
+        st = tv.lib().tvreg_upn_unrolled_fwd(G.handle, ctypes.c_void_p(bd.data_ptr()),
+                                             ctypes.byref(p), 3, 5, None, None,
+                                             ctypes.c_void_p(xK.data_ptr()),
+                                             ctypes.c_void_p(tape.data_ptr()), tape.numel(),
+                                             None)
+        assert st == tv.EINVAL, (method, box)
