@@ -7,7 +7,11 @@ step by step over the first 25 iterations from x0 = 0:
 * FP32 storage with FP64 reductions: the same L sequence, and iterates within
   2e-5 of the oracle's scale (FP32 rounding of the vectors, amplified by the
   momentum steps; measured 1.1e-6 and 8.6e-7; FP64 3.4e-14).
+
+Converged: against the oracle's minimiser (a stored fixture, see below).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -44,3 +48,34 @@ def test_cone64_upn_steps_match_oracle(run, prec):
     err = np.max(np.abs(x.cpu().double().numpy() - xo)) / np.max(np.abs(xo))
     print(f"cone64 alpha={w.alpha} prec={prec}: max rel err {err:.3e}", flush=True)
     assert err <= (1e-9 if prec == tv.F64 else 2e-5)
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("alpha", [1e-2, 1e-3])
+def test_cone64_upn_converges_to_oracle_minimiser(alpha):
+    """UPN to a 1e-6 relative gradient map, FP32 storage with FP64 reductions
+    and plain FP64, against the oracle's minimiser (UPN at 1e-8, stored by
+    golden/make_cone64_xstar.py): the FP32 path is as close as the FP64 path
+    stopped at the same tolerance (the distance is the tolerance's, not the
+    precision's), and the FP64 path at 1e-8 is within 1e-4."""
+    path = os.path.join(GOLDEN, f"cone64_xstar_a{alpha:g}.npy")
+    x_star = np.load(path).astype(np.float64)
+    w = synth.cfg_cone64(alpha)
+    og = oracle.Geometry(w.geom)
+    b = oracle.noisy_data(og, w.phantom(), w.unit_noise(), w.eta)
+    rel = {}
+    for prec, eps in ((tv.F32, 1e-6), (tv.F64, 1e-6), (tv.F64, 1e-8)):
+        dt = torch.float64 if prec == tv.F64 else torch.float32
+        G = tv.Geometry(w.geom, prec)
+        x, info, _ = tv.solve(G, torch.from_numpy(b).to("cuda", dt), method=tv.UPN,
+                              alpha=w.alpha, tau=w.tau, eps=eps, max_iter=20000)
+        assert info["stop_reason"] == tv.OK
+        xg = x.cpu().double().numpy()
+        rel[(prec, eps)] = np.linalg.norm(xg - x_star) / np.linalg.norm(x_star)
+        print(f"cone64 alpha={alpha} prec={prec} eps={eps:g}: iters {info['iters']} "
+              f"rel-L2 {rel[(prec, eps)]:.3e} max-abs {np.max(np.abs(xg - x_star)):.3e}",
+              flush=True)
+    assert rel[(tv.F32, 1e-6)] <= max(3.0 * rel[(tv.F64, 1e-6)], 1e-5)
+    assert rel[(tv.F64, 1e-8)] <= 1e-4
