@@ -56,13 +56,21 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
     iz = min(max(iz, 0), g.nz - 1);
 
     const bool px = ce.Dx > 0.0, py = ce.Dy > 0.0, pz = re.Dz > 0.0;
-    const double sxd = px ? 1.0 : -1.0, syd = py ? 1.0 : -1.0, szd = pz ? 1.0 : -1.0;
+    // An axis the ray runs parallel to gets the crossing offset +inf:
+    // fma(X, 0, +inf) = +inf, so its crossing is never reached.
+    const double ox = ce.invDx != 0.0 ? ce.ox : INFINITY;
+    const double oy = ce.invDy != 0.0 ? ce.oy : INFINITY;
+    const double oz = re.invDz != 0.0 ? re.oz : INFINITY;
+    // Plane steps +-1.0 by their high words (the low word of +-1.0 is zero).
+    const int hx = px ? 0x3ff00000 : (int)0xbff00000;
+    const int hy = py ? 0x3ff00000 : (int)0xbff00000;
+    const int hz = pz ? 0x3ff00000 : (int)0xbff00000;
     double Xn = lox + (double)(ix + (px ? 1 : 0));
     double Yn = loy + (double)(iy + (py ? 1 : 0));
     double Zn = loz + (double)(iz + (pz ? 1 : 0));
-    double tnx = ce.invDx != 0.0 ? plane_t(Xn, ce.invDx, ce.ox) : INFINITY;
-    double tny = ce.invDy != 0.0 ? plane_t(Yn, ce.invDy, ce.oy) : INFINITY;
-    double tnz = re.invDz != 0.0 ? plane_t(Zn, re.invDz, re.oz) : INFINITY;
+    double tnx = plane_t(Xn, ce.invDx, ox);
+    double tny = plane_t(Yn, ce.invDy, oy);
+    double tnz = plane_t(Zn, re.invDz, oz);
     const int sz = g.nx * g.ny;
     const int stx = px ? sx : -sx;
     const int sty = py ? sy : -sy;
@@ -80,16 +88,15 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
             break;
         const bool ax = tnx <= tn, ay = tny <= tn, az = tnz <= tn;
         idx += (ax ? stx : 0) + (ay ? sty : 0) + (az ? stz : 0);
-        const double Xa = Xn + sxd, Ya = Yn + syd, Za = Zn + szd;
-        const double ta = plane_t(Xa, ce.invDx, ce.ox);
-        const double tb = plane_t(Ya, ce.invDy, ce.oy);
-        const double tc = plane_t(Za, re.invDz, re.oz);
-        Xn = ax ? Xa : Xn;
-        Yn = ay ? Ya : Yn;
-        Zn = az ? Za : Zn;
-        tnx = ax ? ta : tnx;
-        tny = ay ? tb : tny;
-        tnz = az ? tc : tnz;
+        // every reached axis moves to its next plane and the others add 0;
+        // all three crossings are then recomputed, an unmoved plane giving
+        // its previous crossing again bit for bit
+        Xn += __hiloint2double(ax ? hx : 0, 0);
+        Yn += __hiloint2double(ay ? hy : 0, 0);
+        Zn += __hiloint2double(az ? hz : 0, 0);
+        tnx = plane_t(Xn, ce.invDx, ox);
+        tny = plane_t(Yn, ce.invDy, oy);
+        tnz = plane_t(Zn, re.invDz, oz);
     }
 }
 
