@@ -277,6 +277,10 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     g.pj_wc = PJ_WC_DEFAULT;
     g.pj_ty = PJ_TY_DEFAULT;
     g.bp_cz = BP_CZ_DEFAULT;
+    g.flat_row = -1;
+    for (int row = 0; cone && row < Rw; ++row)
+        if (rowt[row].invDz == 0.0)
+            g.flat_row = row;
     // partial sums sized for every projector tile shape the tuner may pick
     G->pstride = std::max({project_blocks_max(g), max_reduce_blocks_vol(g.nx, g.ny, g.nz),
                            elementwise_blocks(N), elementwise_blocks(m)});

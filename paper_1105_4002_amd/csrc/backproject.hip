@@ -35,11 +35,13 @@ constexpr int TILE_C = 48;  // detector columns a block stages per view
 constexpr int TILE_R = 32;  // detector rows a block stages per view
 constexpr int TILE_S = TILE_C + 1;  // odd row stride (in doubles) against bank conflicts
 
-// The block's LDS copy of one view.
+// The block's LDS copy of one view.  Row TILE_R of rt and iDz is a zero row
+// (value 0, slope 1) that the cone gather reads for candidate rows outside
+// a voxel's range: it adds exactly nothing.
 struct Tile {
-    double rt[TILE_R * TILE_S];                     // r |D|, [row - R0][col - C0]
+    double rt[(TILE_R + 1) * TILE_S];               // r |D|, [row - R0][col - C0]
     double Sx[TILE_C], Sy[TILE_C], iDx[TILE_C], iDy[TILE_C], ox[TILE_C], oy[TILE_C];
-    double Sz[TILE_R], iDz[TILE_R], oz[TILE_R];
+    double Sz[TILE_R], iDz[TILE_R + 1], oz[TILE_R];
 };
 
 // Data sources of the generic gather: the block's tile, or global memory.
@@ -66,24 +68,28 @@ struct TileSrc {
 };
 
 // Cone-beam gather of one view from the block's tile.  The source sits at
-// z = 0 (Sz = 0, so the plane parameter is Z * invDz; a row with w = 0 runs
-// in the plane z = 0 and belongs to the layer containing 0).
-template <int CZ>
+// z = 0 (Sz = 0, so the plane parameter is Z * invDz).  A row with w = 0 runs
+// in the plane z = 0 and belongs to the layer containing 0; FLAT compiles
+// that case in (only a view whose rows include it needs it).  A candidate
+// row outside the voxel's range (ok false) reads the tile's zero row.  The
+// interval length is clamped at 0 and weights the value in one fma.
+template <bool FLAT>
 __device__ __forceinline__ void cone_row(const Tile &T_, int row, int R0, int cc, double Z0,
-                                         double Z1, double tl, double th, bool in0, bool ok,
-                                         double &acc)
+                                         double Z1, double tl, double th, double flat_len,
+                                         bool ok, double &acc)
 {
-    const int rr = ok ? row - R0 : 0;
+    const int rr = ok ? row - R0 : TILE_R;
     const double val = T_.rt[rr * TILE_S + cc];
     const double idz = T_.iDz[rr];
     const double t0 = Z0 * idz, t1 = Z1 * idz;
     const double lo = fmax(tl, fmin(t0, t1)), hi = fmin(th, fmax(t0, t1));
-    double len = idz != 0.0 ? hi - lo : (in0 ? th - tl : 0.0);
-    len = ok ? len : 0.0;
-    acc += len > 0.0 ? len * val : 0.0;
+    double len = hi - lo;
+    if (FLAT)
+        len = idz != 0.0 ? len : flat_len;
+    acc = fma(fmax(len, 0.0), val, acc);
 }
 
-template <int CZ>
+template <int CZ, bool FLAT>
 __device__ __forceinline__ void gather_cone_tile(const GeomDev &g, const Tile &T_, double c,
                                                  double s, double X0, double X1, double Y0,
                                                  double Y1, int iz0, int C0, int C1, int R0,
@@ -112,11 +118,12 @@ __device__ __forceinline__ void gather_cone_tile(const GeomDev &g, const Tile &T
             if (iz0 + k < g.nz) {  // block-uniform
                 int r_lo, r_hi;
                 index_range(fmin(qa, qb) + g.rv0, fmax(pa, pb) + g.rv0, R0, R1, r_lo, r_hi);
-                const bool in0 = Z0 <= 0.0 && 0.0 < Z1;
-                cone_row<CZ>(T_, r_lo, R0, cc, Z0, Z1, tl, th, in0, r_lo <= r_hi, acc[k]);
-                cone_row<CZ>(T_, r_lo + 1, R0, cc, Z0, Z1, tl, th, in0, r_lo + 1 <= r_hi, acc[k]);
+                const double fl = FLAT && Z0 <= 0.0 && 0.0 < Z1 ? th - tl : 0.0;
+                cone_row<FLAT>(T_, r_lo, R0, cc, Z0, Z1, tl, th, fl, r_lo <= r_hi, acc[k]);
+                cone_row<FLAT>(T_, r_lo + 1, R0, cc, Z0, Z1, tl, th, fl, r_lo + 1 <= r_hi,
+                               acc[k]);
                 for (int row = r_lo + 2; row <= r_hi; ++row)  // wide footprints only
-                    cone_row<CZ>(T_, row, R0, cc, Z0, Z1, tl, th, in0, true, acc[k]);
+                    cone_row<FLAT>(T_, row, R0, cc, Z0, Z1, tl, th, fl, true, acc[k]);
             }
             Z0 = Z1;
             qa = pa;
@@ -186,6 +193,12 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
     const double bX1 = fmin(bX0 + BP_TX, g.hx), bY1 = fmin(bY0 + BP_TY, g.hy);
     const double bZ1 = fmin(bZ0 + CZ, g.hz);
     const size_t view_stride = (size_t)g.rows * g.cols;
+    if (CONE) {  // the zero row; the first view's barrier orders it before any read
+        for (int i = tid; i < TILE_S; i += BP_THREADS)
+            tile.rt[TILE_R * TILE_S + i] = 0.0;
+        if (tid == 0)
+            tile.iDz[TILE_R] = 1.0;
+    }
 
     for (int v = 0; v < g.nviews; ++v) {
         const double c = g.cs[v].x, s = g.cs[v].y;
@@ -230,7 +243,12 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
             __syncthreads();
             if (active) {
                 if (CONE) {
-                    gather_cone_tile<CZ>(g, tile, c, s, X0, X1, Y0, Y1, iz0, C0, C1, R0, R1, acc);
+                    if (g.flat_row >= R0 && g.flat_row <= R1)  // block-uniform
+                        gather_cone_tile<CZ, true>(g, tile, c, s, X0, X1, Y0, Y1, iz0, C0, C1,
+                                                   R0, R1, acc);
+                    else
+                        gather_cone_tile<CZ, false>(g, tile, c, s, X0, X1, Y0, Y1, iz0, C0,
+                                                    C1, R0, R1, acc);
                 } else {
                     const TileSrc src{&tile, C0, R0};
                     gather_view<false, CZ>(g, src, c, s, X0, X1, Y0, Y1, iz0, C0, C1, R0, R1,

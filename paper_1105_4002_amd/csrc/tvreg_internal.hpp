@@ -65,6 +65,7 @@ struct GeomDev {
     int pj_wc;                 // projector: detector columns of a wave's ray tile (8, 16, 32, 64)
     int pj_ty;                 // projector: ray tiles (waves) per block, stacked along rows (1, 2, 4, 8)
     int bp_cz;                 // on-the-fly backprojector: voxels per thread along z (4, 8, 16)
+    int flat_row;              // cone: the detector row with w = 0 (invDz = 0), else -1
 };
 
 // default tile shapes (the batched solve always uses these)
