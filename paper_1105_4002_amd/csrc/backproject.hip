@@ -74,11 +74,11 @@ struct TileSrc {
 // row outside the voxel's range (ok false) reads the tile's zero row.  The
 // interval length is clamped at 0 and weights the value in one fma.
 template <bool FLAT>
-__device__ __forceinline__ void cone_row(const Tile &T_, int row, int R0, int cc, double Z0,
-                                         double Z1, double tl, double th, double flat_len,
-                                         bool ok, double &acc)
+__device__ __forceinline__ void cone_row(const Tile &T_, int rel, int cc, double Z0, double Z1,
+                                         double tl, double th, double flat_len, bool ok,
+                                         double &acc)
 {
-    const int rr = ok ? row - R0 : TILE_R;
+    const int rr = ok ? rel : TILE_R;
     const double val = T_.rt[rr * TILE_S + cc];
     const double idz = T_.iDz[rr];
     const double t0 = Z0 * idz, t1 = Z1 * idz;
@@ -99,6 +99,10 @@ __device__ __forceinline__ void gather_cone_tile(const GeomDev &g, const Tile &T
     u_footprint<true>(g, c, s, X0, X1, Y0, Y1, f0, f1, bmin, bmax);
     int c_lo, c_hi;
     index_range(f0, f1, C0, C1, c_lo, c_hi);
+    // row coordinate w / pv + rv0, shifted to the tile and widened by the
+    // candidate margin, and the tile's last row
+    const double row_lo_off = g.rv0 - (double)R0 - 1e-6, row_hi_off = g.rv0 - (double)R0 + 1e-6;
+    const double row_last = (double)(R1 - R0);
     for (int col = c_lo; col <= c_hi; ++col) {
         const int cc = col - C0;
         double tl, th;
@@ -116,14 +120,14 @@ __device__ __forceinline__ void gather_cone_tile(const GeomDev &g, const Tile &T
             const double Z1 = Z0 + 1.0;
             const double pa = Z1 * itl, pb = Z1 * ith;
             if (iz0 + k < g.nz) {  // block-uniform
-                int r_lo, r_hi;
-                index_range(fmin(qa, qb) + g.rv0, fmax(pa, pb) + g.rv0, R0, R1, r_lo, r_hi);
+                // candidate rows relative to the tile (empty when hi < lo)
+                const int lo = (int)fmax(ceil(fmin(qa, qb) + row_lo_off), 0.0);
+                const int hi = (int)fmin(floor(fmax(pa, pb) + row_hi_off), row_last);
                 const double fl = FLAT && Z0 <= 0.0 && 0.0 < Z1 ? th - tl : 0.0;
-                cone_row<FLAT>(T_, r_lo, R0, cc, Z0, Z1, tl, th, fl, r_lo <= r_hi, acc[k]);
-                cone_row<FLAT>(T_, r_lo + 1, R0, cc, Z0, Z1, tl, th, fl, r_lo + 1 <= r_hi,
-                               acc[k]);
-                for (int row = r_lo + 2; row <= r_hi; ++row)  // wide footprints only
-                    cone_row<FLAT>(T_, row, R0, cc, Z0, Z1, tl, th, fl, true, acc[k]);
+                cone_row<FLAT>(T_, lo, cc, Z0, Z1, tl, th, fl, lo <= hi, acc[k]);
+                cone_row<FLAT>(T_, lo + 1, cc, Z0, Z1, tl, th, fl, lo + 1 <= hi, acc[k]);
+                for (int rel = lo + 2; rel <= hi; ++rel)  // wide footprints only
+                    cone_row<FLAT>(T_, rel, cc, Z0, Z1, tl, th, fl, true, acc[k]);
             }
             Z0 = Z1;
             qa = pa;
