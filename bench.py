@@ -76,9 +76,9 @@ VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s
 # vector instructions per voxel step of the projector's walk loop (count of the
 # gfx950 code the build emits for project_kernel: 3 min, 1 compare and the loop
 # exit; 3 compares, 3 selects and 2 adds for the index; 3 high-word selects,
-# 1 move, 3 adds and 3 FMAs for the planes and next crossings; length, load
-# address, convert and accumulate)
-PROJECT_VALU_PER_STEP = 31
+# 1 move, 3 adds and 3 FMAs for the planes and next crossings; length, move,
+# load address, convert and accumulate)
+PROJECT_VALU_PER_STEP = 30
 
 
 def log(msg: str) -> None:

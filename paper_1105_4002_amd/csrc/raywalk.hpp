@@ -21,7 +21,7 @@ __device__ __forceinline__ void slab(double lo, double hi, double S, double invD
     }
 }
 
-// Visits the ray's voxels in order, calling visit(index, dt) with dt the
+// Visits the ray's voxels in order, calling visit(index, dt) with dt >= 0 the
 // parameter length inside the voxel (multiply by |D| for the length; dt may be
 // 0 where two crossings coincide).  Walks voxel to voxel: the next
 // crossing of each axis is plane_t(X) of the next plane X, the segment ends
@@ -78,11 +78,15 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
     const unsigned last = (unsigned)(g.nx * g.ny * g.nz - 1);
     int idx = ix * sx + iy * sy + iz * sz;
 
-    double t = tmin;
+    // Every crossing after the first is >= the one before it (fma rounds
+    // monotonically and invD has the sign of the plane step), so segment
+    // lengths are >= 0; the first crossing may round to before tmin, and
+    // starting t at the smaller of the two gives that segment length 0.
+    double t = fmin(tmin, fmin(fmin(tnx, tny), fmin(tnz, tmax)));
     const int cap = g.nx + g.ny + g.nz + 2;  // hard bound on the number of voxels
     for (int it = 0; it < cap; ++it) {
         const double tn = fmin(fmin(tnx, tny), fmin(tnz, tmax));
-        visit(min((unsigned)idx, last), fmax(tn - t, 0.0));
+        visit(min((unsigned)idx, last), tn - t);
         t = tn;
         if (!(t < tmax))
             break;
