@@ -86,7 +86,9 @@ typedef struct tvreg_geometry tvreg_geometry; /* opaque, library-owned */
 
 /*
  * Builds the device-side ray tables of a geometry (a few doubles per view,
- * detector column and row; the only memory the library allocates).
+ * detector column and row; the only device memory the library allocates;
+ * tvreg_solve and the unrolled UPN calls hold a page-locked host copy of
+ * their few scalar sums for the duration of the call).
  * Returns TVREG_EINVAL for non-positive sizes or pitches, NULL pointers, or a
  * cone whose source or detector is inside the volume's bounding sphere.
  * Synchronous.

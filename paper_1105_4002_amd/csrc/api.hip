@@ -468,7 +468,7 @@ struct Runner {
     double *part;
     int pstride;
     double *dsc;        // device scalars [S_COUNT]
-    double hs[S_COUNT]; // host copy
+    HostScalars hs;     // host copy
     SlotList pend;
     bool prof = false;
     struct Ev {
@@ -544,8 +544,8 @@ struct Runner {
     {
         TVR_HIP(launch_finalize(pend, part, pstride, st));
         pend.n = 0;
-        TVR_HIP(hipMemcpyAsync(hs, dsc, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
-        TVR_HIP(hipStreamSynchronize(st));
+        TVR_HIP(hipMemcpyAsync(hs.p, dsc, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
+        TVR_HIP(spin_sync(st, hs.done));
         resolve();
         return TVREG_OK;
     }
@@ -952,6 +952,8 @@ static tvreg_status solve_impl(const tvreg_geometry *G, const T *b, const tvreg_
     s.run.pstride = G->pstride;
     s.run.dsc = (double *)(ws + L.scalars);
     s.run.pend.n = 0;
+    if (!s.run.hs.p)
+        return fail(TVREG_ENOMEM, "page-locked host buffer of %d doubles", (int)S_COUNT);
     {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         s.run.prof = g_prof.on;

@@ -79,6 +79,50 @@ struct DeviceGuard {
     }
 };
 
+// Waits for the work queued on st so far by polling an event from this
+// thread (the solvers wait on the device after every line-search trial; a
+// blocking wait adds the thread's wake-up latency to each of them).
+inline hipError_t spin_sync(hipStream_t st, hipEvent_t ev)
+{
+    hipError_t e = hipEventRecord(ev, st);
+    if (e != hipSuccess)
+        return e;
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    return e;
+}
+
+// Page-locked host copy of the scalar sums a solver reads back after each
+// line-search trial (a copy into pageable memory is staged and costs far more
+// than the copy itself), with the event its reads wait on.  p is null when
+// the allocation failed.
+struct HostScalars {
+    double *p = nullptr;
+    hipEvent_t done = nullptr;  // polled by spin_sync after each read
+    HostScalars()
+    {
+        if (hipHostMalloc((void **)&p, sizeof(double) * S_COUNT, hipHostMallocDefault) !=
+            hipSuccess)
+            p = nullptr;
+        if (p && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(p);
+            p = nullptr;
+            done = nullptr;
+        }
+    }
+    ~HostScalars()
+    {
+        if (done)
+            (void)hipEventDestroy(done);
+        if (p)
+            (void)hipHostFree(p);
+    }
+    HostScalars(const HostScalars &) = delete;
+    HostScalars &operator=(const HostScalars &) = delete;
+    double &operator[](int i) { return p[i]; }
+    double operator[](int i) const { return p[i]; }
+};
+
 }  // namespace tvr
 
 #define TVR_HIP(call)                                                                          \

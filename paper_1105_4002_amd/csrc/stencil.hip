@@ -479,6 +479,39 @@ __global__ __launch_bounds__(256) void extrapolate_grouped(BatchProblem<T> *prob
     block_reduce_store<1>(red, P.part, P.pstride, slots, lb);
 }
 
+// Finalisers: one block of FB threads per slot sums the slot's per-block
+// partials in a fixed order, so every sum is bitwise reproducible.  Thread t
+// adds the partials t, t + FB, t + 2 FB, ... in four interleaved chains (four
+// loads in flight), the chains combine pairwise, each wave reduces by a fixed
+// shuffle tree and thread 0 adds the wave totals in order.  The single and
+// batched finalisers share it, so a batched problem's sums equal its own
+// solve's.
+constexpr int FB = 1024;
+
+__device__ __forceinline__ double fixed_order_sum(const double *__restrict__ src, int count)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * FB < count; i += 4 * FB) {
+        a0 += src[i];
+        a1 += src[i + FB];
+        a2 += src[i + 2 * FB];
+        a3 += src[i + 3 * FB];
+    }
+    for (; i < count; i += FB)
+        a0 += src[i];
+    const double s = wave_sum((a0 + a1) + (a2 + a3));
+    __shared__ double sh[FB / 64];
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < FB / 64; ++w)
+            t += sh[w];
+    return t;
+}
+
 // Batched finaliser: one block per (problem, slot) of the slots the round
 // produced.
 constexpr int NFIN = 10;
@@ -486,7 +519,7 @@ __constant__ const int fin_slots[NFIN] = {S_XD2, S_GD, S_TVB, S_BRB, S_R2, S_RD2
                                           S_TVY, S_BRY, S_XY2, S_RY2};
 
 template <typename T>
-__global__ __launch_bounds__(VB) void finalize_grouped(BatchProblem<T> *probs)
+__global__ __launch_bounds__(FB) void finalize_grouped(BatchProblem<T> *probs)
 {
     const int p = blockIdx.x / NFIN, q = blockIdx.x % NFIN;
     const BatchProblem<T> &P = probs[p];
@@ -504,21 +537,9 @@ __global__ __launch_bounds__(VB) void finalize_grouped(BatchProblem<T> *probs)
         count = P.nb_vox;
     if (count == 0)
         return;
-    const double *src = P.part + (size_t)slot * P.pstride;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < count; i += VB)
-        s += src[i];
-    __shared__ double sh[VB / 64];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0)
-        sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < VB / 64; ++w)
-            t += sh[w];
+    const double t = fixed_order_sum(P.part + (size_t)slot * P.pstride, count);
+    if (threadIdx.x == 0)
         P.sum[slot] = t;
-    }
 }
 
 template <typename T>
@@ -572,26 +593,13 @@ __global__ __launch_bounds__(VB) void clip_kernel(int64_t n, const T *__restrict
         out[i] = (T)clip_box((double)in[i], box);
 }
 
-__global__ __launch_bounds__(VB) void finalize_kernel(SlotList sl, const double *__restrict__ partials,
+__global__ __launch_bounds__(FB) void finalize_kernel(SlotList sl, const double *__restrict__ partials,
                                                       int pstride)
 {
     const int q = blockIdx.x;
-    const int slot = sl.slot[q], count = sl.count[q];
-    const double *p = partials + (size_t)slot * pstride;
-    double red[1] = {0.0};
-    for (int i = threadIdx.x; i < count; i += VB)
-        red[0] += p[i];
-    __shared__ double sh[VB / 64];
-    double s = wave_sum(red[0]);
-    if ((threadIdx.x & 63) == 0)
-        sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < VB / 64; ++w)
-            t += sh[w];
+    const double t = fixed_order_sum(partials + (size_t)sl.slot[q] * pstride, sl.count[q]);
+    if (threadIdx.x == 0)
         *sl.dst[q] = t;
-    }
 }
 
 __global__ void combine_phi_kernel(const double *r2, const double *tv, double alpha, double *out)
@@ -692,7 +700,7 @@ hipError_t launch_finalize(const SlotList &sl, const double *partials, int pstri
 {
     if (sl.n <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3(sl.n), dim3(VB), 0, st, sl, partials, pstride);
+    hipLaunchKernelGGL(finalize_kernel, dim3(sl.n), dim3(FB), 0, st, sl, partials, pstride);
     return hipGetLastError();
 }
 
@@ -743,7 +751,7 @@ hipError_t launch_extrapolate_grouped(BatchProblem<T> *probs, const int *offs, i
 template <typename T>
 hipError_t launch_finalize_grouped(BatchProblem<T> *probs, int n, hipStream_t st)
 {
-    hipLaunchKernelGGL((finalize_grouped<T>), dim3(n * NFIN), dim3(VB), 0, st, probs);
+    hipLaunchKernelGGL((finalize_grouped<T>), dim3(n * NFIN), dim3(FB), 0, st, probs);
     return hipGetLastError();
 }
 

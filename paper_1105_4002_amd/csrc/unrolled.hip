@@ -83,7 +83,7 @@ struct Unroller {
     TapeLayout lay;
     int64_t N, m;
     double *part, *dsum;
-    double hs[S_COUNT];
+    HostScalars hs;  // host copy of the sums
     SlotList pend;
 
     T *vecN(size_t base, int i) const
@@ -113,8 +113,8 @@ struct Unroller {
     {
         TVR_HIP(launch_finalize(pend, part, G->pstride, st));
         pend.n = 0;
-        TVR_HIP(hipMemcpyAsync(hs, dsum, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
-        TVR_HIP(hipStreamSynchronize(st));
+        TVR_HIP(hipMemcpyAsync(hs.p, dsum, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
+        TVR_HIP(spin_sync(st, hs.done));
         return TVREG_OK;
     }
 
@@ -421,6 +421,8 @@ extern "C" tvreg_status tvreg_upn_unrolled_fwd(const tvreg_geometry *G, const vo
         u.m = G->m;
         u.part = (double *)((char *)tape + lay.part);
         u.dsum = (double *)((char *)tape + lay.sums);
+        if (!u.hs.p)
+            return fail(TVREG_ENOMEM, "page-locked host buffer of %d doubles", (int)S_COUNT);
         return u.forward(L_replay, L_out, (T *)xK, rec.data(), p, &stall);
     };
     const tvreg_status s = G->prec == TVREG_F64 ? run(double()) : run(float());
@@ -486,6 +488,8 @@ extern "C" tvreg_status tvreg_upn_unrolled_bwd(const tvreg_geometry *G, const vo
         u.m = G->m;
         u.part = (double *)((char *)tape + lay.part);
         u.dsum = (double *)((char *)tape + lay.sums);
+        if (!u.hs.p)
+            return fail(TVREG_ENOMEM, "page-locked host buffer of %d doubles", (int)S_COUNT);
         return u.backward(rec.data(), (const T *)xK_bar, (T *)dl_db, dl_dlogalpha);
     };
     return G->prec == TVREG_F64 ? run(double()) : run(float());
