@@ -348,6 +348,102 @@ def unrolled_leg(tv, synth, torch, dev, reps: int = 3):
             "reverse_ms": round(1e3 * tb / reps, 2)}
 
 
+def small_leg(tv, synth, torch, dev, tol: float) -> dict:
+    """The small workloads on the GPU, stored A^T and default tile shapes:
+    gradient evaluations per second (100 evaluations at x_true, FP32) and time
+    to the relative gradient-map tolerance from x0 = 0 (UPN in FP32 and FP64;
+    also GP and GPBB on parallel24, at most 5000 iterations).  Data: the
+    projection of the phantom plus the seeded noise, as for the headline."""
+    cases = [("parallel24", synth.cfg_small_parallel(), ["gp", "gpbb", "upn"]),
+             ("cone64_a0.01", synth.cfg_cone64(1e-2), ["upn"]),
+             ("cone64_a0.001", synth.cfg_cone64(1e-3), ["upn"]),
+             ("cone64_30views", synth.cfg_unrolled(), ["upn"])]
+    methods = {"gp": tv.GP, "gpbb": tv.GPBB, "upn": tv.UPN}
+    out = {}
+    for name, w, solves in cases:
+        g = w.geom
+        x_true = torch.from_numpy(w.phantom()).to(dev)
+        G64, G32 = tv.Geometry(g, tv.F64), tv.Geometry(g, tv.F32)
+        ax = tv.project(G64, x_true)
+        sigma = w.eta * torch.linalg.vector_norm(ax).item() / math.sqrt(g.n_rays)
+        b64 = ax + sigma * torch.from_numpy(w.unit_noise()).to(dev)
+        b32 = b64.to(torch.float32).contiguous()
+        G32.attach_matrix()
+        G64.attach_matrix()
+        x32 = x_true.to(torch.float32)
+        for _ in range(5):
+            tv.objective_grad(G32, b32, w.alpha, w.tau, x32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(100):
+            tv.objective_grad(G32, b32, w.alpha, w.tau, x32)
+        torch.cuda.synchronize()
+        rec = {"grad_evals_per_s": round(100 / (time.perf_counter() - t0), 1)}
+        for mth in solves:
+            for label, G, bb in (("f32", G32, b32), ("f64", G64, b64)):
+                ws = tv.solve_workspace(G, methods[mth])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info, _ = tv.solve(G, bb, method=methods[mth], alpha=w.alpha, tau=w.tau,
+                                      eps=tol, max_iter=5000, workspace=ws)
+                torch.cuda.synchronize()
+                rec[f"time_to_tol_{mth}_{label}"] = {
+                    "seconds": round(time.perf_counter() - t0, 3), "iters": info["iters"],
+                    "status": info["stop_reason"]}
+        log(f"  {name}: {rec}")
+        out[name] = rec
+        del G32, G64
+    return out
+
+
+def oracle_table(evals_only: bool) -> dict:
+    """CPU oracle timings per workload (FP64, the host's OpenMP threads): gradient
+    evaluations per second at x_true, and time to the 1e-6 relative gradient-map
+    tolerance from x0 = 0 (GP, GPBB and UPN on parallel24; UPN on the 64^3 cone
+    scans).  The 32-problem batch gets one gradient of every problem; its
+    solves (about 38 000 gradient evaluations in all) are not run.  Touches no GPU."""
+    import oracle
+    import synth
+    out = {"threads": oracle.num_threads(), "configs": {}}
+    cases = [("parallel24", synth.cfg_small_parallel(), ["gp", "gpbb", "upn"]),
+             ("cone64_a0.01", synth.cfg_cone64(1e-2), ["upn"]),
+             ("cone64_a0.001", synth.cfg_cone64(1e-3), ["upn"]),
+             ("cone64_30views", synth.cfg_unrolled(), ["upn"]),
+             ("cone256", synth.cfg_cone256(), [])]
+    methods = {"gp": oracle.GP, "gpbb": oracle.GPBB, "upn": oracle.UPN}
+    for name, w, solves in cases:
+        og = oracle.Geometry(w.geom)
+        b = oracle.noisy_data(og, w.phantom(), w.unit_noise(), w.eta)
+        x = w.phantom()
+        n, t0 = 0, time.perf_counter()
+        while True:
+            oracle.phi_grad(og, b, w.alpha, w.tau, x)
+            n += 1
+            if time.perf_counter() - t0 >= 3.0 or (n >= 1 and name == "cone256"):
+                break
+        rec = {"grad_evals_per_s": round(n / (time.perf_counter() - t0), 4)}
+        log(f"oracle {name}: {rec['grad_evals_per_s']} gradient evals/s")
+        if not evals_only:
+            for mth in solves:
+                t0 = time.perf_counter()
+                _, info, _ = oracle.solve(og, b, method=methods[mth], alpha=w.alpha, tau=w.tau,
+                                          eps=1e-6, max_iter=5000)
+                rec[f"time_to_tol_{mth}"] = {"seconds": round(time.perf_counter() - t0, 2),
+                                             "iters": info["iters"], "status": info["status"]}
+                log(f"oracle {name} {mth}: {rec[f'time_to_tol_{mth}']}")
+        out["configs"][name] = rec
+    t0 = time.perf_counter()
+    for w in synth.cfg_batch():
+        og = oracle.Geometry(w.geom)
+        b = oracle.noisy_data(og, w.phantom(), w.unit_noise(), w.eta)
+        oracle.phi_grad(og, b, w.alpha, w.tau, w.phantom())
+    dt = time.perf_counter() - t0
+    out["configs"]["batch32"] = {"one_gradient_of_each_s": round(dt, 2),
+                                 "note": "includes building each problem's data"}
+    log(f"oracle batch32: one gradient of each problem {dt:.1f} s")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,6 +472,12 @@ def main() -> int:
     ap.add_argument("--methods", action="store_true",
                     help="also time GP and GPBB (FP32 and FP64) to tolerance")
     ap.add_argument("--methods-max-iter", type=int, default=3000)
+    ap.add_argument("--small", action="store_true",
+                    help="also time the small workloads (parallel24, the 64^3 cone scans)")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="CPU only: time the FP64 oracle on every workload, on all host threads "
+                         "and (in a child process) on one, and print that table instead")
+    ap.add_argument("--oracle-evals-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--paper", action="store_true",
                     help="also run the paper's 64^3 experiment (55 and 19 sphere views)")
     args = ap.parse_args()
@@ -385,6 +487,22 @@ def main() -> int:
               "sharding of this path is a design note, not an implemented mode.",
               file=sys.stderr)
         return 2
+
+    if args.oracle_table or args.oracle_evals_only:
+        table = oracle_table(args.oracle_evals_only)
+        if args.oracle_table:
+            import subprocess
+            env = dict(os.environ, OMP_NUM_THREADS="1")
+            log("the same gradient evaluations on one thread (child process)")
+            child = subprocess.run([sys.executable, os.path.abspath(__file__),
+                                    "--oracle-evals-only"], env=env, capture_output=True,
+                                   text=True, check=True)
+            one = json.loads(child.stdout.strip().splitlines()[-1])
+            for name, rec in one["configs"].items():
+                key = "grad_evals_per_s" if "grad_evals_per_s" in rec else "one_gradient_of_each_s"
+                table["configs"][name][key + "_1thread"] = rec[key]
+        print(json.dumps(table), flush=True)
+        return 0
 
     import numpy as np
     import torch
@@ -591,6 +709,9 @@ def main() -> int:
                 del ws
                 if label == "f64" and stored:
                     G.detach_matrix()
+    if args.small:
+        log(f"small workloads: gradient evals/s and time to {args.tol:g}")
+        result["small"] = small_leg(tv, synth, torch, dev, args.tol)
     if args.paper:
         log("the paper's experiment: 64^3, 55 and 19 views over the sphere, GP/GPBB/UPN FP64")
         result["paper_experiment"] = paper_leg(tv, synth, torch, dev)
