@@ -15,8 +15,9 @@
 // Memory: per view, a block (16 x 16 voxel columns x CZ) stages in LDS the
 // detector tile its voxels can see -- r |D| in double, the tile's column ray
 // entries (structure of arrays) and row entries -- so the inner loops read
-// only LDS.  The cone-beam inner loop is branch free: every candidate row
-// gets the exact interval arithmetic, selected to zero where it is empty.
+// only LDS.  The cone-beam inner loop is branch free: the two candidate rows
+// of each layer get the exact interval arithmetic, a row outside the range
+// reads the tile's zero row, and a non-positive length adds nothing.
 // A view whose footprint exceeds the tile (unusual geometries) takes the
 // generic arithmetic with global loads.
 #include "gather.hpp"
