@@ -265,7 +265,8 @@ size_t tvreg_solve_workspace_bytes(const tvreg_geometry *geom, tvreg_method meth
  * b_dev: m values of T.  The line-search decisions and the mu estimate are
  * evaluated in the rearranged form Bregman_f(x, y) vs L/2 |x - y|^2 (the
  * same inequality as Alg. 2 / eq. 9 without subtracting two objective
- * values).  Synchronises `stream` once per line-search trial and before
+ * values).  Synchronises `stream` once per line-search trial (the calling
+ * thread polls an event, so it stays busy while the device works) and before
  * returning; `info` is written on the host.  Returns TVREG_OK,
  * TVREG_ENOTCONV or TVREG_ESTALL, or a negative error.
  */
