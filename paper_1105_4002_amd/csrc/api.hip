@@ -998,7 +998,7 @@ struct MatLayout {
 MatLayout mat_layout(const tvreg_geometry *G, int64_t ev)
 {
     MatLayout L{};
-    L.sv = (G->N + 63) / 64;
+    L.sv = mat_slices(G->g.nx, G->g.ny, G->g.nz);
     L.ev = ev;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1022,9 +1022,9 @@ tvreg_status count_entries(const tvreg_geometry *G, int32_t *cnt_v, int32_t *w_v
 {
     GeomDev g = G->g;
     g.mat = MatDev{};
-    const int64_t sv = (G->N + 63) / 64;
+    const int64_t sv = mat_slices(g.nx, g.ny, g.nz);
     TVR_HIP(launch_matrix_count(g, cnt_v, st));
-    TVR_HIP(launch_slice_widths(cnt_v, G->N, w_v, st));
+    TVR_HIP(launch_slice_widths(g, cnt_v, w_v, st));
     std::vector<int32_t> wv((size_t)sv);
     TVR_HIP(hipMemcpyAsync(wv.data(), w_v, sizeof(int32_t) * wv.size(), hipMemcpyDeviceToHost, st));
     std::vector<int32_t> cv;

@@ -10,15 +10,19 @@
 // keeps its on-the-fly walk: it reads no matrix at all and beats streaming
 // a ray-major copy (measured: 2.3 ms against 3.6 ms on the 256^3 scan).
 //
-// Layout (SELL-64): voxels in natural order are cut into slices of 64 (one
-// wavefront); entry k of lane l of slice s sits at off[s] + 64 k + l, so
-// every step of a wavefront loads 64 consecutive values and indices.  A
-// slice is as wide as its longest lane; shorter lanes are padded with zero
-// weights on a ray index they already read, so the product loop is branch
-// free.  The entries of a voxel follow the gather's order (views, then
-// detector columns, then rows): a_ij = (t_exit - t_enter) |D_i| from the
-// gather's enumeration, rounded once to T.  The product accumulates in
-// double.
+// Layout: sliced ELLPACK with 8 x 8 voxel tiles as slices (one wavefront;
+// the mapping is mat_slot / mat_voxel); entry k of lane l of slice s sits at
+// off[s] + 64 k + l, so every step of a wavefront loads 64 consecutive
+// values and indices.  A tile's voxels project onto a compact detector
+// patch in every view, which keeps a step's gathers of r within a few cache
+// lines (measured on the 256^3 scan: 2.27 ms against 2.77 ms for slices of
+// 64 consecutive voxels along x).  A slice is as wide as its longest lane;
+// shorter lanes are padded with zero weights on a ray index they already
+// read, so the product loop is branch free; lanes of an edge tile past the
+// volume have width 0.  The entries of a voxel follow the gather's order
+// (views, then detector columns, then rows): a_ij = (t_exit - t_enter) |D_i|
+// from the gather's enumeration, rounded once to T.  The product
+// accumulates in double.
 #include "gather.hpp"
 #include "ray3d.hpp"
 #include "reduce.hpp"
@@ -73,17 +77,21 @@ __global__ __launch_bounds__(CT_TX *CT_TY) void count_voxels_kernel(GeomDev g,
             cnt[(size_t)(iz0 + k) * plane + (size_t)iy * g.nx + ix] = n[k];
 }
 
-// one wavefront per slice of 64
-__global__ __launch_bounds__(MB) void slice_width_kernel(const int32_t *__restrict__ cnt,
-                                                         int64_t n, int32_t *__restrict__ w)
+// one wavefront per slice
+__global__ __launch_bounds__(MB) void slice_width_kernel(int nx, int ny, int64_t sv,
+                                                         const int32_t *__restrict__ cnt,
+                                                         int32_t *__restrict__ w)
 {
     const int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x;
-    int c = i < n ? cnt[i] : 0;
+    const int64_t s = i >> 6;
+    int x, y, z, c = 0;
+    if (s < sv && mat_voxel(nx, ny, s, (int)(i & 63), x, y, z))
+        c = cnt[((size_t)z * ny + y) * nx + x];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         c = max(c, __shfl_xor(c, off, 64));
-    if ((threadIdx.x & 63) == 0 && i < n)
-        w[i >> 6] = c;
+    if ((threadIdx.x & 63) == 0 && s < sv)
+        w[s] = c;
 }
 
 // ------------------------------------------------------------------ filling
@@ -104,9 +112,11 @@ __global__ __launch_bounds__(CT_TX *CT_TY) void fill_voxels_kernel(GeomDev g, T 
     int32_t last[CT_CZ];
 #pragma unroll
     for (int k = 0; k < CT_CZ; ++k) {
-        const int64_t j = (int64_t)(iz0 + k < g.nz ? iz0 + k : 0) * plane + (size_t)iy * g.nx + ix;
-        pos[k] = g.mat.off_v[j >> 6] + (j & 63);
-        end[k] = pos[k] + 64 * (int64_t)g.mat.w_v[j >> 6];
+        int64_t s;
+        int l;
+        mat_slot(g.nx, g.ny, ix, iy, iz0 + k < g.nz ? iz0 + k : 0, s, l);
+        pos[k] = g.mat.off_v[s] + l;
+        end[k] = pos[k] + 64 * (int64_t)g.mat.w_v[s];
         last[k] = 0;
     }
     for (int v = 0; v < g.nviews; ++v) {
@@ -141,19 +151,21 @@ __global__ __launch_bounds__(CT_TX *CT_TY) void fill_voxels_kernel(GeomDev g, T 
 
 // ---------------------------------------------------------- sparse products
 
-// x = A^T r, one thread per voxel; block `blk` of the product
+// x = A^T r, one thread per voxel (lane of a tile slice); block `blk` of the
+// product
 template <typename T>
 __device__ __forceinline__ void spmv_voxels_block(const GeomDev &g, const T *__restrict__ r,
                                                   T *__restrict__ out, int blk)
 {
-    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
     const int64_t j = (int64_t)blk * MB + threadIdx.x;
     const int64_t s = j >> 6;
     if (s >= g.mat.sv)
         return;
+    int x, y, z;
+    const bool in = mat_voxel(g.nx, g.ny, s, (int)(j & 63), x, y, z);
     const T *__restrict__ val = (const T *)g.mat.val_v + g.mat.off_v[s] + (j & 63);
     const int32_t *__restrict__ idx = g.mat.idx_v + g.mat.off_v[s] + (j & 63);
-    const int w = j < N ? g.mat.w_v[s] : 0;  // lanes past the last voxel hold no entries
+    const int w = in ? g.mat.w_v[s] : 0;  // lanes past the volume hold no entries
     double acc = 0.0;
     // the matrix is read once per product: non-temporal loads keep it from
     // evicting r, which every voxel gathers from
@@ -163,8 +175,8 @@ __device__ __forceinline__ void spmv_voxels_block(const GeomDev &g, const T *__r
         const int32_t i = __builtin_nontemporal_load(idx + 64 * k);
         acc = fma((double)a, (double)r[i], acc);
     }
-    if (j < N)
-        out[j] = (T)acc;
+    if (in)
+        out[((size_t)z * g.ny + y) * g.nx + x] = (T)acc;
 }
 
 template <typename T>
@@ -190,7 +202,7 @@ int blocks_for(int64_t n) { return (int)((n + MB - 1) / MB); }
 
 }  // namespace
 
-int matrix_product_blocks(const GeomDev &g) { return blocks_for((int64_t)g.nx * g.ny * g.nz); }
+int matrix_product_blocks(const GeomDev &g) { return blocks_for(64 * mat_slices(g.nx, g.ny, g.nz)); }
 
 template <typename T>
 hipError_t launch_spmv_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
@@ -203,8 +215,8 @@ hipError_t launch_spmv_grouped(BatchProblem<T> *probs, const int *offs, int n, i
 template <typename T>
 hipError_t launch_backproject_matrix(const GeomDev &g, const T *r, T *out, hipStream_t st)
 {
-    const int nb = blocks_for((int64_t)g.nx * g.ny * g.nz);
-    hipLaunchKernelGGL((spmv_voxels_kernel<T>), dim3(nb), dim3(MB), 0, st, g, r, out);
+    hipLaunchKernelGGL((spmv_voxels_kernel<T>), dim3(matrix_product_blocks(g)), dim3(MB), 0, st, g,
+                       r, out);
     return hipGetLastError();
 }
 
@@ -220,9 +232,11 @@ hipError_t launch_matrix_count(const GeomDev &g, int32_t *cnt_v, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_slice_widths(const int32_t *cnt, int64_t n, int32_t *w, hipStream_t st)
+hipError_t launch_slice_widths(const GeomDev &g, const int32_t *cnt, int32_t *w, hipStream_t st)
 {
-    hipLaunchKernelGGL(slice_width_kernel, dim3(blocks_for(n)), dim3(MB), 0, st, cnt, n, w);
+    const int64_t sv = mat_slices(g.nx, g.ny, g.nz);
+    hipLaunchKernelGGL(slice_width_kernel, dim3(blocks_for(64 * sv)), dim3(MB), 0, st, g.nx, g.ny,
+                       sv, cnt, w);
     return hipGetLastError();
 }
 

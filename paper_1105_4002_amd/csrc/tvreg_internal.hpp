@@ -34,9 +34,39 @@ struct View3 {
     double dx, dy, dz, ux, uy, uz, vx, vy, vz, idx, idy, idz;
 };
 
-// Optional stored transpose A^T in SELL-64 form (slices of 64 consecutive
-// voxels; entry k of lane l of slice s at off[s] + 64 k + l): values
-// a_ij = length |D_i| as T, ray indices int32.
+// Optional stored transpose A^T in a sliced-ELLPACK form whose slices are
+// 8 x 8 voxel tiles of one z-plane (one wavefront each; tiles ordered x,
+// then y, then z; lane l = 8 (y % 8) + x % 8; entry k of lane l of slice s
+// at off[s] + 64 k + l): values a_ij = length |D_i| as T, ray indices int32.
+// A tile's voxels project onto a compact detector patch in every view, so a
+// wavefront's gathers of r stay within few cache lines.
+constexpr int MAT_T = 8;  // tile side
+
+__host__ __device__ __forceinline__ int64_t mat_slices(int nx, int ny, int nz)
+{
+    return (int64_t)((nx + MAT_T - 1) / MAT_T) * ((ny + MAT_T - 1) / MAT_T) * nz;
+}
+
+// slice and lane of voxel (x, y, z)
+__host__ __device__ __forceinline__ void mat_slot(int nx, int ny, int x, int y, int z, int64_t &s,
+                                                  int &l)
+{
+    const int tx = (nx + MAT_T - 1) / MAT_T, ty = (ny + MAT_T - 1) / MAT_T;
+    s = ((int64_t)z * ty + y / MAT_T) * tx + x / MAT_T;
+    l = (y % MAT_T) * MAT_T + x % MAT_T;
+}
+
+// voxel of lane l of slice s; false for lanes of an edge tile past the volume
+__host__ __device__ __forceinline__ bool mat_voxel(int nx, int ny, int64_t s, int l, int &x,
+                                                   int &y, int &z)
+{
+    const int tx = (nx + MAT_T - 1) / MAT_T, ty = (ny + MAT_T - 1) / MAT_T;
+    x = (int)(s % tx) * MAT_T + l % MAT_T;
+    y = (int)((s / tx) % ty) * MAT_T + l / MAT_T;
+    z = (int)(s / ((int64_t)tx * ty));
+    return x < nx && y < ny;
+}
+
 struct MatDev {
     int present;                     // 0: A^T evaluated on the fly
     int64_t sv;                      // slices of voxels
@@ -173,8 +203,8 @@ template <typename T>
 hipError_t launch_backproject_matrix(const GeomDev &g, const T *r, T *out, hipStream_t st);
 // entries per voxel (the counting pass of the build)
 hipError_t launch_matrix_count(const GeomDev &g, int32_t *cnt_v, hipStream_t st);
-// slice widths w[s] = max of cnt over the slice's 64 lanes
-hipError_t launch_slice_widths(const int32_t *cnt, int64_t n, int32_t *w, hipStream_t st);
+// slice widths w[s] = max of cnt (natural voxel order) over the slice's lanes
+hipError_t launch_slice_widths(const GeomDev &g, const int32_t *cnt, int32_t *w, hipStream_t st);
 // fills values and ray indices at the offsets of g.mat
 template <typename T>
 hipError_t launch_matrix_fill(const GeomDev &g, T *val_v, int32_t *idx_v, hipStream_t st);
