@@ -74,11 +74,11 @@ FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed 
 # vector instruction issue: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s
 # vector instructions per voxel step of the projector's walk loop (count of the
-# gfx950 code the build emits for project_kernel: 3 min, 1 compare and the loop
-# exit; 3 compares, 3 selects and 2 adds for the index; 3 high-word selects,
-# 1 move, 3 adds and 3 FMAs for the planes and next crossings; length, move,
-# load address, convert and accumulate)
-PROJECT_VALU_PER_STEP = 30
+# gfx950 code the build emits for project_kernel on volumes under 2 GiB: 3 min,
+# 1 compare and the loop exit; 3 compares, 3 selects and 2 adds for the index;
+# 3 high-word selects, 3 adds and 3 FMAs for the planes and next crossings;
+# length, move, 32-bit load offset, convert and accumulate)
+PROJECT_VALU_PER_STEP = 28
 
 
 def log(msg: str) -> None:

@@ -57,8 +57,9 @@ __device__ __forceinline__ void decode_block(int L, int gx, int nviews, int &bx,
     by = L / (gx * nviews);
 }
 
-// One block: WC detector columns x (TY * 64 / WC) rows of view v.
-template <typename T, bool CONE, int WC, int TY>
+// One block: WC detector columns x (TY * 64 / WC) rows of view v; BUF picks
+// the walk's load path (see ray_walk).
+template <typename T, bool CONE, int WC, int TY, bool BUF>
 __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restrict__ x,
                                               const T *__restrict__ xt, const T *__restrict__ b,
                                               T *__restrict__ out, const T *__restrict__ rref,
@@ -80,8 +81,8 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
         // rays mostly along x read the y-fastest copy when one is given
         const double cv = g.cs[v].x, sv = g.cs[v].y;
         const bool use_t = xt != nullptr && fabs(cv) > fabs(sv);
-        const double s = ray_walk<T, CONE>(g, use_t ? xt : x, ce, re, use_t ? g.ny : 1,
-                                           use_t ? 1 : g.nx);
+        const double s = ray_walk<T, CONE, BUF>(g, use_t ? xt : x, ce, re, use_t ? g.ny : 1,
+                                                use_t ? 1 : g.nx);
         const double dn = CONE ? g.dnorm[(size_t)row * g.cols + col] : g.dnorm[v];
         const size_t i = ((size_t)v * g.rows + row) * g.cols + col;
         double ri = s * dn;
@@ -100,7 +101,7 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
     }
 }
 
-template <typename T, bool CONE, int WC, int TY>
+template <typename T, bool CONE, int WC, int TY, bool BUF>
 __global__ __launch_bounds__(64 * TY) void project_kernel(GeomDev g, const T *__restrict__ x,
                                                               const T *__restrict__ xt,
                                                               const T *__restrict__ b,
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(64 * TY) void project_kernel(GeomDev g, const T *__
     const int L = xcd_contiguous(blockIdx.x, gridDim.x);
     int bx, by, v;
     decode_block(L, (g.cols + WC - 1) / WC, g.nviews, bx, by, v);
-    project_block<T, CONE, WC, TY>(g, x, xt, b, out, rref, partials, pstride, bx, by, v, L);
+    project_block<T, CONE, WC, TY, BUF>(g, x, xt, b, out, rref, partials, pstride, bx, by, v, L);
 }
 
 // Batched: the trial points XB of every running problem (residual against
@@ -130,11 +131,11 @@ __global__ __launch_bounds__(64 * PJ_TY_DEFAULT) void project_grouped(BatchProbl
     int bx, by, v;
     decode_block(local, (P.g.cols + WC - 1) / WC, P.g.nviews, bx, by, v);
     if (P.g.cone)
-        project_block<T, true, WC, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx,
-                                       by, v, local);
+        project_block<T, true, WC, TY, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
+                                              P.pstride, bx, by, v, local);
     else
-        project_block<T, false, WC, TY>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part, P.pstride, bx,
-                                        by, v, local);
+        project_block<T, false, WC, TY, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
+                                               P.pstride, bx, by, v, local);
 }
 
 }  // namespace
@@ -167,12 +168,19 @@ void launch_shape(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,
 {
     dim3 block(64, TY, 1);
     dim3 grid(grid_blocks(g, WC, TY), 1, 1);  // decoded in the kernel
-    if (g.cone)
-        hipLaunchKernelGGL((project_kernel<T, true, WC, TY>), grid, block, 0, st, g, x, xt, b,
-                           out, rref, partials, pstride);
+    const bool buf = walk_buffer_ok(g, sizeof(T));
+    if (g.cone && buf)
+        hipLaunchKernelGGL((project_kernel<T, true, WC, TY, true>), grid, block, 0, st, g, x, xt,
+                           b, out, rref, partials, pstride);
+    else if (g.cone)
+        hipLaunchKernelGGL((project_kernel<T, true, WC, TY, false>), grid, block, 0, st, g, x, xt,
+                           b, out, rref, partials, pstride);
+    else if (buf)
+        hipLaunchKernelGGL((project_kernel<T, false, WC, TY, true>), grid, block, 0, st, g, x,
+                           xt, b, out, rref, partials, pstride);
     else
-        hipLaunchKernelGGL((project_kernel<T, false, WC, TY>), grid, block, 0, st, g, x, xt, b,
-                           out, rref, partials, pstride);
+        hipLaunchKernelGGL((project_kernel<T, false, WC, TY, false>), grid, block, 0, st, g, x,
+                           xt, b, out, rref, partials, pstride);
 }
 
 template <typename T, int WC>

@@ -32,7 +32,7 @@ __device__ __forceinline__ void slab(double lo, double hi, double S, double invD
 // The volume is read through strides (sx, sy) so that a y-fastest copy can
 // serve views whose rays run mostly along x (adjacent detector columns then
 // touch adjacent addresses).
-template <bool CONE, class Visit>
+template <bool CONE, bool CLAMP, class Visit>
 __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry &ce,
                                                const RowEntry &re, int sx, int sy, Visit &&visit)
 {
@@ -86,7 +86,7 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
     const int cap = g.nx + g.ny + g.nz + 2;  // hard bound on the number of voxels
     for (int it = 0; it < cap; ++it) {
         const double tn = fmin(fmin(tnx, tny), fmin(tnz, tmax));
-        visit(min((unsigned)idx, last), tn - t);
+        visit(CLAMP ? min((unsigned)idx, last) : (unsigned)idx, tn - t);
         t = tn;
         if (!(t < tmax))
             break;
@@ -104,16 +104,55 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
     }
 }
 
-// Sum of dt * x along the ray (the projector's ray sum before |D|).
-template <typename T, bool CONE>
+// Loads of x[idx] through a buffer resource: the hardware checks each offset
+// against the volume's size (an offset past it reads 0), so the walk needs no
+// clamp of its index and addresses with a 32-bit offset.  Word 3 of the
+// descriptor is the gfx9-family value for raw dword access (32-bit data
+// format, no swizzle).
+constexpr int BUF_WORD3 = 0x00020000;
+
+template <typename T>
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned idx);
+template <>
+__device__ __forceinline__ double buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned idx)
+{
+    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(idx * 4u), 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned idx)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(idx * 8u), 0, 0));
+}
+
+// Sum of dt * x along the ray (the projector's ray sum before |D|).  With
+// BUF (volumes under 2^31 bytes: a buffer offset is a signed 32-bit number)
+// x is read through a range-checked buffer resource, otherwise through
+// clamped global loads; both read the same values.
+template <typename T, bool CONE, bool BUF>
 __device__ __forceinline__ double ray_walk(const GeomDev &g, const T *__restrict__ x,
                                            const ColEntry &ce, const RowEntry &re, int sx,
                                            int sy)
 {
     double acc = 0.0;
-    ray_walk_visit<CONE>(g, ce, re, sx, sy,
-                         [&](unsigned idx, double dt) { acc = fma(dt, (double)x[idx], acc); });
+    if (BUF) {
+        const int bytes = (int)(sizeof(T) * (size_t)g.nx * g.ny * g.nz);
+        const __amdgpu_buffer_rsrc_t xr =
+            __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, bytes, BUF_WORD3);
+        ray_walk_visit<CONE, false>(g, ce, re, sx, sy, [&](unsigned idx, double dt) {
+            acc = fma(dt, buf_load<T>(xr, idx), acc);
+        });
+    } else {
+        ray_walk_visit<CONE, true>(g, ce, re, sx, sy, [&](unsigned idx, double dt) {
+            acc = fma(dt, (double)x[idx], acc);
+        });
+    }
     return acc;
+}
+
+// whether a volume of this geometry fits the buffer path
+__host__ __device__ __forceinline__ bool walk_buffer_ok(const GeomDev &g, size_t elem)
+{
+    return elem * (size_t)g.nx * g.ny * g.nz < (size_t(1) << 31);
 }
 
 }  // namespace tvr
