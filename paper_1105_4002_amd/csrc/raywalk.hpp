@@ -31,7 +31,8 @@ __device__ __forceinline__ void slab(double lo, double hi, double S, double invD
 // slab exit, so no index leaves the volume before t reaches tmax.
 // The volume is read through strides (sx, sy) so that a y-fastest copy can
 // serve views whose rays run mostly along x (adjacent detector columns then
-// touch adjacent addresses).
+// touch adjacent addresses).  CLAMP clamps each visited index to the volume
+// as well (for loads without a hardware range check).
 template <bool CONE, bool CLAMP, class Visit>
 __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry &ce,
                                                const RowEntry &re, int sx, int sy, Visit &&visit)
@@ -116,7 +117,8 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned id
 template <>
 __device__ __forceinline__ double buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned idx)
 {
-    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(idx * 4u), 0, 0));
+    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(idx * 4u), 0, 0);
+    return (double)__builtin_bit_cast(float, v);
 }
 template <>
 __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned idx)
