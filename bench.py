@@ -105,7 +105,7 @@ def kernel_model(name: str, N: int, m: int, nnz: int, es: int, stored: bool):
     if name == "trial":
         return "hbm", es * 3.0 * N, "GB/s", HBM_PEAK       # z, g in, xbar out
     if name == "extrapolate":
-        return "hbm", es * 3.0 * (N + m) / 2.0, "GB/s", HBM_PEAK  # mean of the N and m launches
+        return "hbm", es * 3.0 * (N + m), "GB/s", HBM_PEAK  # volume and residual, one launch
     if name == "transpose":
         return "hbm", es * 2.0 * N, "GB/s", HBM_PEAK       # volume in, y-fastest copy out
     raise KeyError(name)

@@ -723,12 +723,8 @@ struct Solver {
                     // y^(k+1) = x^(k+1) + beta (x^(k+1) - x^(k)), and its residual
                     int nb = 0;
                     TVR_HIP(run.timed(TVREG_KERNEL_EXTRAPOLATE, [&] {
-                        return launch_extrapolate<T>(N, beta, XB, X, Ybuf, nullptr, 0, run.st,
-                                                     nullptr);
-                    }));
-                    TVR_HIP(run.timed(TVREG_KERNEL_EXTRAPOLATE, [&] {
-                        return launch_extrapolate<T>(m, beta, RXB, RX, RYbuf, run.part,
-                                                     run.pstride, run.st, &nb);
+                        return launch_extrapolate2<T>(N, XB, X, Ybuf, m, RXB, RX, RYbuf, beta,
+                                                      run.part, run.pstride, run.st, &nb);
                     }));
                     run.add(S_RY2, nb);
                     have_ry2 = true;

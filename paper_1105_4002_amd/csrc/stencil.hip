@@ -565,6 +565,37 @@ __global__ __launch_bounds__(VB) void extrapolate_kernel(int64_t n, double beta,
     }
 }
 
+// UPN's extrapolation of the volume and of its residual in one launch:
+// blocks [0, nb1) take y1 = xn1 + beta (xn1 - xo1) over n1 voxels; blocks
+// [nb1, nb1 + nb2) take y2 likewise over n2 rays and write the partial sums
+// of (y2 - xn2)^2 exactly as a launch of nb2 blocks of extrapolate_kernel
+// would (same elements per block, same slots).
+template <typename T>
+__global__ __launch_bounds__(VB) void extrapolate2_kernel(
+    int64_t n1, const T *__restrict__ xn1, const T *__restrict__ xo1, T *__restrict__ y1, int nb1,
+    int64_t n2, const T *__restrict__ xn2, const T *__restrict__ xo2, T *__restrict__ y2, int nb2,
+    double beta, double *__restrict__ partials, int pstride)
+{
+    if ((int)blockIdx.x < nb1) {  // block-uniform
+        for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n1; i += (int64_t)nb1 * VB) {
+            const double a = (double)xn1[i];
+            y1[i] = (T)(a + beta * (a - (double)xo1[i]));
+        }
+        return;
+    }
+    const int b = (int)blockIdx.x - nb1;
+    double red[1] = {0.0};
+    for (int64_t i = (int64_t)b * VB + threadIdx.x; i < n2; i += (int64_t)nb2 * VB) {
+        const double a = (double)xn2[i];
+        const T yi = (T)(a + beta * (a - (double)xo2[i]));
+        y2[i] = yi;
+        const double d = (double)yi - a;
+        red[0] += d * d;
+    }
+    const int slots[1] = {S_RY2};
+    block_reduce_store<1>(red, partials, pstride, slots, b);
+}
+
 template <typename T>
 __global__ __launch_bounds__(VB) void bb_dots_kernel(int64_t n, const T *__restrict__ x,
                                                      const T *__restrict__ xp,
@@ -664,6 +695,18 @@ hipError_t launch_extrapolate(int64_t n, double beta, const T *xn, const T *xo, 
         *nblocks = nb;
     hipLaunchKernelGGL((extrapolate_kernel<T>), dim3(nb), dim3(VB), 0, st, n, beta, xn, xo, y,
                        partials, pstride);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_extrapolate2(int64_t n1, const T *xn1, const T *xo1, T *y1, int64_t n2,
+                               const T *xn2, const T *xo2, T *y2, double beta, double *partials,
+                               int pstride, hipStream_t st, int *nblocks2)
+{
+    const int nb1 = elementwise_blocks(n1), nb2 = elementwise_blocks(n2);
+    *nblocks2 = nb2;
+    hipLaunchKernelGGL((extrapolate2_kernel<T>), dim3(nb1 + nb2), dim3(VB), 0, st, n1, xn1, xo1, y1,
+                       nb1, n2, xn2, xo2, y2, nb2, beta, partials, pstride);
     return hipGetLastError();
 }
 
@@ -776,6 +819,9 @@ TVR_INST_GROUPED(double)
                                         double, Box, T *, double *, int, hipStream_t, int *);   \
     template hipError_t launch_extrapolate<T>(int64_t, double, const T *, const T *, T *,       \
                                               double *, int, hipStream_t, int *);               \
+    template hipError_t launch_extrapolate2<T>(int64_t, const T *, const T *, T *, int64_t,      \
+                                               const T *, const T *, T *, double, double *, int,  \
+                                               hipStream_t, int *);                              \
     template hipError_t launch_bb_dots<T>(int64_t, const T *, const T *, const T *, const T *,  \
                                           double *, int, hipStream_t, int *);                   \
     template hipError_t launch_clip<T>(int64_t, const T *, T *, Box, hipStream_t);              \

@@ -179,6 +179,12 @@ hipError_t launch_trial(int nx, int ny, int nz, double tau, const T *z, const T 
 template <typename T>
 hipError_t launch_extrapolate(int64_t n, double beta, const T *xn, const T *xo, T *y,
                               double *partials, int pstride, hipStream_t st, int *nblocks);
+// the volume's and the residual's extrapolation in one launch (partials of
+// the second as launch_extrapolate writes them; *nblocks2 = their count)
+template <typename T>
+hipError_t launch_extrapolate2(int64_t n1, const T *xn1, const T *xo1, T *y1, int64_t n2,
+                               const T *xn2, const T *xo2, T *y2, double beta, double *partials,
+                               int pstride, hipStream_t st, int *nblocks2);
 
 // slots S_SS, S_SY of s = x - xp, dg = g - gp.
 template <typename T>
