@@ -4,11 +4,12 @@
 //
 // The paper takes A as given (the system matrix of Sec. II-A).  The gather
 // backprojector spends most of its time re-deriving each ray/voxel length
-// from the geometry (about 130 FP64 instructions per voxel and view); with
+// from the geometry (about 115 vector instructions per voxel and view); with
 // 288 GB of HBM per GPU the voxel-major copy of a 256^3 scan (1.3e9
-// non-zeros, 12 GB in FP32) is cheaper to stream.  The forward projector
-// keeps its on-the-fly walk: it reads no matrix at all and beats streaming
-// a ray-major copy (measured: 2.3 ms against 3.6 ms on the 256^3 scan).
+// non-zeros, 12 GB in FP32) is cheaper to stream (2.4 ms against 3.7 ms).
+// The forward projector keeps its on-the-fly walk: it reads no matrix at
+// all and beats streaming a ray-major copy (1.9 ms; a ray-major product
+// measured 3.6 ms on the 256^3 scan).
 //
 // Layout: sliced ELLPACK with 8 x 8 voxel tiles as slices (one wavefront;
 // the mapping is mat_slot / mat_voxel); entry k of lane l of slice s sits at
