@@ -54,7 +54,11 @@ def _desc(tv, **kw):
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(det_rows=0), dict(pitch_u=0.0),
                                  dict(pitch_v=-1.0), dict(src_to_centre=5.0),
-                                 dict(src_to_det=33.0), dict(beam=7)])
+                                 dict(src_to_det=33.0), dict(beam=7),
+                                 # size limits: voxel and ray indices are 32-bit
+                                 dict(nx=2048, ny=2048, nz=512),
+                                 dict(det_cols=65536, det_rows=16384),
+                                 dict(nx=1 << 20, ny=1, nz=1)])
 def test_create_geometry_rejects_bad_descriptors(tv, bad):
     d, _keep = _desc(tv, **bad)
     h = ctypes.c_void_p()
