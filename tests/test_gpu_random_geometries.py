@@ -1,9 +1,13 @@
 """Seeded random small scans of all three beams (parallel about z, cone,
 parallel along directions over the sphere) with ragged volume and detector
 sizes, arbitrary pitches, angles and directions: the projector, the on-the-fly
-backprojector and the stored A^T against the FP64 oracle (FP64 within 1e-12 of
-the output scale; non-zero count of the stored transpose within the
-coincident-crossing slivers of the oracle's)."""
+backprojector and the stored A^T against the FP64 oracle.  FP64: within 1e-12
+of the output scale.  FP32 storage: the oracle is applied to the same
+FP32-rounded inputs, and each output may differ by 2^-24 of (|ref| + the
+oracle applied to the absolute input: the rounding of each stored length and
+of the output) plus 1e-9 of the scale for the FP64 accumulation order.  The
+stored transpose's non-zero count equals the oracle's up to the
+coincident-crossing slivers."""
 import math
 
 import numpy as np
@@ -39,23 +43,34 @@ def random_geometry(seed):
                           dirs=d)
 
 
+def close(got, ref, absref, prec):
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    if prec == tv.F64:
+        return np.max(np.abs(got - ref)) <= 1e-12 * scale
+    return bool(np.all(np.abs(got - ref) <= 2.0 ** -24 * (absref + np.abs(ref)) + 1e-9 * scale))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("seed", range(24))
-def test_random_geometry_operators_match_oracle(seed):
+def test_random_geometry_operators_match_oracle(seed, prec):
     g = random_geometry(seed)
-    print(f"seed {seed}: beam {g.beam}, volume {g.nx}x{g.ny}x{g.nz}, {g.n_views} views, "
+    print(f"seed {seed} {prec}: beam {g.beam}, volume {g.nx}x{g.ny}x{g.nz}, {g.n_views} views, "
           f"detector {g.det_cols}x{g.det_rows}", flush=True)
+    P = tv.F64 if prec == "f64" else tv.F32
+    dt = torch.float64 if prec == "f64" else torch.float32
     rng = np.random.default_rng(2000 + seed)
     x = rng.uniform(0.0, 1.0, (g.nz, g.ny, g.nx))
     r = rng.standard_normal(g.proj_shape)
-    G = tv.Geometry(g, tv.F64)
-    xd = torch.from_numpy(x).to("cuda")
-    rd = torch.from_numpy(r).to("cuda")
+    if prec == "f32":  # the oracle sees the same rounded inputs
+        x, r = x.astype(np.float32).astype(np.float64), r.astype(np.float32).astype(np.float64)
+    G = tv.Geometry(g, P)
+    xd = torch.from_numpy(x).to("cuda", dt)
+    rd = torch.from_numpy(r).to("cuda", dt)
     y_ref, b_ref = oracle.project(g, x), oracle.backproject(g, r)
-    ys = max(np.max(np.abs(y_ref)), 1e-300)
-    bs = max(np.max(np.abs(b_ref)), 1e-300)
-    assert np.max(np.abs(tv.project(G, xd).cpu().numpy() - y_ref)) <= 1e-12 * ys
-    assert np.max(np.abs(tv.backproject(G, rd).cpu().numpy() - b_ref)) <= 1e-12 * bs
+    b_abs = oracle.backproject(g, np.abs(r))
+    assert close(tv.project(G, xd).cpu().double().numpy(), y_ref, y_ref, P)
+    assert close(tv.backproject(G, rd).cpu().double().numpy(), b_ref, b_abs, P)
     nnz = G.attach_matrix()
     ref_nnz = oracle.nnz(g)
     assert abs(nnz - ref_nnz) <= 4e-6 * ref_nnz + 16, (nnz, ref_nnz)
-    assert np.max(np.abs(tv.backproject(G, rd).cpu().numpy() - b_ref)) <= 1e-12 * bs
+    assert close(tv.backproject(G, rd).cpu().double().numpy(), b_ref, b_abs, P)
