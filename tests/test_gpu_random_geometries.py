@@ -74,3 +74,30 @@ def test_random_geometry_operators_match_oracle(seed, prec):
     ref_nnz = oracle.nnz(g)
     assert abs(nnz - ref_nnz) <= 4e-6 * ref_nnz + 16, (nnz, ref_nnz)
     assert close(tv.backproject(G, rd).cpu().double().numpy(), b_ref, b_abs, P)
+
+
+@pytest.mark.parametrize("stored", [False, True])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+def test_random_geometry_upn_steps_match_oracle_fp64(seed, stored):
+    """25 UPN steps (FP64) on a random scan take the oracle's steps: the same
+    line-search L sequence and iterates within 1e-9 of their scale, with the
+    backprojection on the fly or from the stored A^T."""
+    g = random_geometry(seed)
+    print(f"seed {seed} stored={stored}: UPN steps, beam {g.beam}, volume {g.nx}x{g.ny}x{g.nz}",
+          flush=True)
+    rng = np.random.default_rng(3000 + seed)
+    og = oracle.Geometry(g)
+    x_true = rng.uniform(0.0, 1.0, (g.nz, g.ny, g.nx))
+    b = oracle.noisy_data(og, x_true, rng.standard_normal(g.proj_shape), 0.01)
+    K, alpha, tau = 25, 1e-2, 1e-2
+    xo, io, ho = oracle.solve(og, b, method=oracle.UPN, alpha=alpha, tau=tau, eps=0.0,
+                              max_iter=K, hist_len=K, bt_form=1)
+    G = tv.Geometry(g, tv.F64)
+    if stored:
+        G.attach_matrix()
+    x, info, h = tv.solve(G, torch.from_numpy(b).to("cuda", torch.float64), method=tv.UPN,
+                          alpha=alpha, tau=tau, eps=0.0, max_iter=K, hist_len=K)
+    assert info["iters"] == io["iters"] == K
+    np.testing.assert_array_equal(np.array(h["L"]), ho["L"][:K])
+    err = np.max(np.abs(x.cpu().numpy() - xo)) / max(np.max(np.abs(xo)), 1e-300)
+    assert err <= 1e-9, err
