@@ -128,3 +128,29 @@ def test_random_geometries_batched_equals_single_fp32():
     for i, (x, info, _) in enumerate(singles):
         assert torch.equal(xb[i], x), i
         assert ib[i]["iters"] == info["iters"], i
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_geometry_unrolled_matches_oracle_fp64(seed):
+    """The differentiated form on a random scan of each beam (FP64, K = 10):
+    the oracle's L sequence, x_K within 1e-10, and dl/dlog(alpha), dl/db
+    within 1e-8 of the oracle's reverse pass for l = |x_K - x_true|^2."""
+    g = random_geometry(seed)
+    print(f"seed {seed}: unrolled, beam {g.beam}, volume {g.nx}x{g.ny}x{g.nz}", flush=True)
+    rng = np.random.default_rng(5000 + seed)
+    og = oracle.Geometry(g)
+    xt = rng.uniform(0.0, 1.0, (g.nz, g.ny, g.nx))
+    b = oracle.noisy_data(og, xt, rng.standard_normal(g.proj_shape), 0.01)
+    K, alpha, tau = 10, 1e-2, 1e-2
+    o = oracle.unrolled(og, b, K, alpha, tau=tau)
+    og_g = oracle.unrolled(og, b, K, alpha, tau=tau, L=o["L"], xK_bar=2.0 * (o["xK"] - xt))
+    G = tv.Geometry(g, tv.F64)
+    bd = torch.from_numpy(b).to("cuda", torch.float64)
+    xK, tape, L = tv.upn_unrolled_fwd(G, bd, K, alpha, tau=tau)
+    np.testing.assert_array_equal(np.array(L), o["L"])
+    xk = xK.cpu().numpy()
+    assert np.linalg.norm(xk - o["xK"]) <= 1e-10 * np.linalg.norm(o["xK"])
+    da, db = tv.upn_unrolled_bwd(G, bd, tape, 2.0 * (xK - torch.from_numpy(xt).to("cuda")))
+    ref = alpha * og_g["alpha_bar"]
+    assert abs(da - ref) <= 1e-8 * abs(ref)
+    assert np.linalg.norm(db.cpu().numpy() - og_g["b_bar"]) <= 1e-8 * np.linalg.norm(og_g["b_bar"])
