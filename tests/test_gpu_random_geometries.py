@@ -154,3 +154,31 @@ def test_random_geometry_unrolled_matches_oracle_fp64(seed):
     ref = alpha * og_g["alpha_bar"]
     assert abs(da - ref) <= 1e-8 * abs(ref)
     assert np.linalg.norm(db.cpu().numpy() - og_g["b_bar"]) <= 1e-8 * np.linalg.norm(og_g["b_bar"])
+
+
+@pytest.mark.parametrize("method", ["gp", "upn"])
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_random_geometry_box_steps_match_oracle_fp64(seed, method):
+    """25 steps of GP or UPN under the box Q = [0.05, 0.8]^N (FP64) on a
+    random scan: the oracle's L sequence, iterates within 1e-9, all in Q."""
+    lo, hi = 0.05, 0.8
+    g = random_geometry(seed)
+    print(f"seed {seed}: {method} in a box, beam {g.beam}", flush=True)
+    rng = np.random.default_rng(6000 + seed)
+    og = oracle.Geometry(g)
+    b = oracle.noisy_data(og, rng.uniform(0.0, 1.0, (g.nz, g.ny, g.nx)),
+                          rng.standard_normal(g.proj_shape), 0.01)
+    tm, om = (tv.GP, oracle.GP) if method == "gp" else (tv.UPN, oracle.UPN)
+    K, alpha, tau = 25, 1e-2, 1e-2
+    xo, io, ho = oracle.solve(og, b, method=om, alpha=alpha, tau=tau, eps=0.0, max_iter=K,
+                              hist_len=K, bt_form=1, lower=lo, upper=hi)
+    G = tv.Geometry(g, tv.F64)
+    x, info, h = tv.solve(G, torch.from_numpy(b).to("cuda", torch.float64), method=tm,
+                          alpha=alpha, tau=tau, eps=0.0, max_iter=K, hist_len=K, lower=lo,
+                          upper=hi)
+    assert info["iters"] == io["iters"]
+    n = len(h["L"])
+    np.testing.assert_array_equal(np.array(h["L"]), ho["L"][:n])
+    xg = x.cpu().numpy()
+    assert xg.min() >= lo and xg.max() <= hi
+    assert np.max(np.abs(xg - xo)) <= 1e-9 * max(np.max(np.abs(xo)), 1.0)
