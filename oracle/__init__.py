@@ -126,11 +126,11 @@ def lib():
         L.og_slab_length.restype = ctypes.c_double
         L.og_ray_endpoints.argtypes = [gp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp]
         L.og_solve.argtypes = [gp, dp, ctypes.POINTER(_Params), dp, ctypes.POINTER(_Info),
-                               dp, dp, dp, dp, ctypes.c_int32]
+                               dp, dp, dp, dp, dp, ctypes.c_int32]
         L.og_solve.restype = ctypes.c_int32
         L.og_solve_dense.argtypes = [ctypes.c_int32] * 4 + [dp, dp, ctypes.POINTER(_Params), dp,
                                                             ctypes.POINTER(_Info), dp, dp, dp,
-                                                            dp, ctypes.c_int32]
+                                                            dp, dp, ctypes.c_int32]
         L.og_solve_dense.restype = ctypes.c_int32
         L.og_num_threads.restype = ctypes.c_int32
         L.og_huber_bregman.argtypes = [dp, dp, dp, ctypes.c_double]
@@ -294,17 +294,23 @@ def default_params(method: int, alpha: float, tau: float = 1e-4, eps: float = 1e
 
 
 def solve(g, b, x0=None, hist_len: int = 0, **params):
-    """Run GP / GPBB / UPN.  Returns (x, info dict, history dict)."""
+    """Run GP / GPBB / UPN.  Returns (x, info dict, history dict).
+
+    History entry k (first hist_len iterations): phi of the accepted point,
+    the relative gradient map, L_k (1/theta_k for GPBB), mu_k, and for UPN
+    theta_{k+1}, the root Alg. 3 computes at iteration k from theta_k and
+    mu_k / L_k (theta_1 = sqrt(mu_0 / L_0) at k = 0).
+    """
     G = _geom(g)
     p = default_params(**params)
     P = _Params(**p)
     info = _Info()
     x = np.zeros(G.vol_shape) if x0 is None else _f64(x0).reshape(G.vol_shape).copy()
     hl = max(int(hist_len), 1)
-    hp, hg, hL, hm = (np.full(hl, np.nan) for _ in range(4))
+    hp, hg, hL, hm, ht = (np.full(hl, np.nan) for _ in range(5))
     lib().og_solve(G.ref, _dp(_f64(b).reshape(G.proj_shape)), ctypes.byref(P), _dp(x),
-                   ctypes.byref(info), _dp(hp), _dp(hg), _dp(hL), _dp(hm), hl)
-    return x, _info_dict(info), dict(phi=hp, gm=hg, L=hL, mu=hm)
+                   ctypes.byref(info), _dp(hp), _dp(hg), _dp(hL), _dp(hm), _dp(ht), hl)
+    return x, _info_dict(info), dict(phi=hp, gm=hg, L=hL, mu=hm, theta=ht)
 
 
 def solve_dense(A, b, vol_shape, x0=None, hist_len: int = 0, **params):
@@ -316,10 +322,10 @@ def solve_dense(A, b, vol_shape, x0=None, hist_len: int = 0, **params):
     info = _Info()
     x = np.zeros(vol_shape) if x0 is None else _f64(x0).reshape(vol_shape).copy()
     hl = max(int(hist_len), 1)
-    hp, hg, hL, hm = (np.full(hl, np.nan) for _ in range(4))
+    hp, hg, hL, hm, ht = (np.full(hl, np.nan) for _ in range(5))
     lib().og_solve_dense(m, nx, ny, nz, _dp(A), _dp(_f64(b)), ctypes.byref(P), _dp(x),
-                         ctypes.byref(info), _dp(hp), _dp(hg), _dp(hL), _dp(hm), hl)
-    return x, _info_dict(info), dict(phi=hp, gm=hg, L=hL, mu=hm)
+                         ctypes.byref(info), _dp(hp), _dp(hg), _dp(hL), _dp(hm), _dp(ht), hl)
+    return x, _info_dict(info), dict(phi=hp, gm=hg, L=hL, mu=hm, theta=ht)
 
 
 def _info_dict(info: _Info) -> dict:

@@ -743,7 +743,7 @@ static int stop_now(const og_params *p, double gm, double gm0, int64_t N)
  */
 static int32_t solve_gp_upn(const og_op *op, const double *b, const og_params *p, double *x,
                             og_info *info, double *hphi, double *hgm, double *hL, double *hmu,
-                            int32_t hlen)
+                            double *htheta, int32_t hlen)
 {
     int64_t N = op->N, m = op->m;
     int nest = p->method == OG_NESTEROV;
@@ -780,6 +780,7 @@ static int32_t solve_gp_upn(const og_op *op, const double *b, const og_params *p
         mu = L; /* theta_1 = 1, then mu_k = 0: the mu = 0 recurrence from its usual start */
     double theta = sqrt(mu / L);
     record(hmu, hlen, 0, mu);
+    record(htheta, hlen, 0, theta);
     double fx_k = 0.0;
     int fx_k_valid = 0;
     if (bt != 0) {
@@ -841,6 +842,7 @@ static int32_t solve_gp_upn(const og_op *op, const double *b, const og_params *p
             theta = theta_n;
         }
         record(hmu, hlen, k, mu);
+        record(htheta, hlen, k, theta); /* theta_{k+1} (UPN), the unchanged start value otherwise */
         /* y^(k+1) = x^(k+1) + beta_k (x^(k+1) - x^(k)) */
         for (int64_t j = 0; j < N; ++j) {
             y[j] = xn[j] + beta * (xn[j] - xk[j]);
@@ -983,31 +985,31 @@ static int32_t solve_gpbb(const og_op *op, const double *b, const og_params *p, 
 
 static int32_t solve_op(const og_op *op, const double *b, const og_params *p, double *x,
                         og_info *info, double *hphi, double *hgm, double *hL, double *hmu,
-                        int32_t hlen)
+                        double *htheta, int32_t hlen)
 {
     memset(info, 0, sizeof(*info));
     for (int64_t j = 0; j < op->N; ++j)
         x[j] = pq_box(x[j], p->lower, p->upper); /* start from a feasible point */
     if (p->method == OG_GPBB)
         return solve_gpbb(op, b, p, x, info, hphi, hgm, hL, hlen);
-    return solve_gp_upn(op, b, p, x, info, hphi, hgm, hL, hmu, hlen);
+    return solve_gp_upn(op, b, p, x, info, hphi, hgm, hL, hmu, htheta, hlen);
 }
 
 int32_t og_solve(const og_geom *g, const double *b, const og_params *p, double *x,
                  og_info *info, double *hist_phi, double *hist_gm, double *hist_L,
-                 double *hist_mu, int32_t hist_len)
+                 double *hist_mu, double *hist_theta, int32_t hist_len)
 {
     og_op op = {n_rays(g), (int64_t)g->nx * g->ny * g->nz, g->nx, g->ny, g->nz, g, NULL};
-    return solve_op(&op, b, p, x, info, hist_phi, hist_gm, hist_L, hist_mu, hist_len);
+    return solve_op(&op, b, p, x, info, hist_phi, hist_gm, hist_L, hist_mu, hist_theta, hist_len);
 }
 
 int32_t og_solve_dense(int32_t m, int32_t nx, int32_t ny, int32_t nz, const double *A,
                        const double *b, const og_params *p, double *x, og_info *info,
                        double *hist_phi, double *hist_gm, double *hist_L, double *hist_mu,
-                       int32_t hist_len)
+                       double *hist_theta, int32_t hist_len)
 {
     og_op op = {m, (int64_t)nx * ny * nz, nx, ny, nz, NULL, A};
-    return solve_op(&op, b, p, x, info, hist_phi, hist_gm, hist_L, hist_mu, hist_len);
+    return solve_op(&op, b, p, x, info, hist_phi, hist_gm, hist_L, hist_mu, hist_theta, hist_len);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -92,13 +92,13 @@ double og_gradmap_norm_box(int64_t n, const double *x, const double *grad, doubl
 /* solvers: GP (eq. 6), GPBB (Alg. 1), UPN (Alg. 3), all with the stop test of Sec. III-D */
 int32_t og_solve(const og_geom *g, const double *b, const og_params *p, double *x,
                  og_info *info, double *hist_phi, double *hist_gm, double *hist_L,
-                 double *hist_mu, int32_t hist_len);
+                 double *hist_mu, double *hist_theta, int32_t hist_len);
 
 /* same solvers on an explicit dense m x (nx*ny*nz) matrix (tiny systems only) */
 int32_t og_solve_dense(int32_t m, int32_t nx, int32_t ny, int32_t nz, const double *A,
                        const double *b, const og_params *p, double *x, og_info *info,
                        double *hist_phi, double *hist_gm, double *hist_L, double *hist_mu,
-                       int32_t hist_len);
+                       double *hist_theta, int32_t hist_len);
 
 /* differentiated form: Hessian-vector product of the smoothed TV, and K
    unrolled UPN steps from x = 0 with the reverse-mode gradient of
