@@ -193,6 +193,25 @@ tvreg_status tvreg_tv_grad(int32_t nx, int32_t ny, int32_t nz, tvreg_precision p
                            void *workspace_dev, size_t workspace_bytes, void *stream);
 
 /*
+ * tvreg_tv_grad without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same kernels, arguments and results as tvreg_tv_grad (bit for
+ * bit); the per-block partial sums of the TV value live in a static device
+ * array of the library instead (about 3.75 MiB, one per device, held until
+ * the process ends).  That array bounds the volume: the TV grid of
+ * ceil(nx/64) x ceil(ny/4) x ceil(nz/16) blocks may have at most 32768
+ * blocks (512^3 voxels fit); larger volumes return TVREG_EINVAL.  Calls on
+ * one device share the array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.  The
+ * call allocates nothing: no hipMalloc, no hipFree, no allocating library
+ * routine.  The first call on a device looks the array's address up
+ * (hipGetSymbolAddress), a synchronous runtime query.
+ */
+tvreg_status tvreg_tv_grad_noalloc(int32_t nx, int32_t ny, int32_t nz, tvreg_precision precision,
+                                   double tau, const void *x_dev, void *grad_dev,
+                                   double *tv_value_dev, void *stream);
+
+/*
  * out_dev = H(y) v, the Hessian of T_tau at y applied to v (the derivative of
  * the gradient above along v): sum_j D_j^T dq_j with dq_j = D_j v / tau where
  * |D_j y| < tau and (e - u (u.e)) / |D_j y|, u = D_j y / |D_j y|, e = D_j v,

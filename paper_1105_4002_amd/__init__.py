@@ -74,7 +74,7 @@ EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
            "tvreg_backproject", "tvreg_matrix_scratch_bytes", "tvreg_matrix_plan",
            "tvreg_matrix_attach", "tvreg_matrix_detach", "tvreg_autotune_workspace_bytes",
            "tvreg_autotune", "tvreg_get_tuning", "tvreg_set_tuning", "tvreg_tv_workspace_bytes",
-           "tvreg_tv_grad", "tvreg_tv_hessvec",
+           "tvreg_tv_grad", "tvreg_tv_grad_noalloc", "tvreg_tv_hessvec",
            "tvreg_objective_workspace_bytes", "tvreg_objective_grad",
            "tvreg_solve_workspace_bytes", "tvreg_solve", "tvreg_solve_batched_workspace_bytes",
            "tvreg_solve_batched", "tvreg_unrolled_workspace_bytes", "tvreg_upn_unrolled_fwd",
@@ -122,6 +122,9 @@ def _load():
     L.tvreg_tv_grad.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int, ctypes.c_double, vp, vp,
                                                        vp, vp, sz, vp]
     L.tvreg_tv_grad.restype = st
+    L.tvreg_tv_grad_noalloc.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int, ctypes.c_double, vp,
+                                                               vp, vp, vp]
+    L.tvreg_tv_grad_noalloc.restype = st
     L.tvreg_tv_hessvec.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_int, ctypes.c_double, vp, vp,
                                                           vp, vp, vp, sz, vp]
     L.tvreg_tv_hessvec.restype = st
@@ -332,6 +335,29 @@ def tv_grad(x: torch.Tensor, tau: float, value: bool = True, grad: bool = True):
                               ctypes.c_void_p(val.data_ptr()) if value else None,
                               ctypes.c_void_p(ws.data_ptr()) if value else None, wsb,
                               _stream(x)), "tvreg_tv_grad")
+    return g, val
+
+
+def tv_grad_noalloc(x: torch.Tensor, tau: float, value: bool = True, grad: bool = True,
+                    out: torch.Tensor = None, value_out: torch.Tensor = None):
+    """tv_grad through tvreg_tv_grad_noalloc: the library takes no workspace
+    (its partial sums live in a static device array).  With `out` and
+    `value_out` given (a tensor like x and a 0-d float64 tensor) nothing is
+    allocated on this side either."""
+    nz, ny, nx = x.shape
+    prec = F64 if x.dtype == torch.float64 else F32
+    n = nx * ny * nz
+    g = (out if out is not None else torch.empty_like(x)) if grad else None
+    val = None
+    if value:
+        val = value_out if value_out is not None else torch.empty(
+            (), dtype=torch.float64, device=x.device)
+        if val.dtype != torch.float64 or val.numel() != 1 or val.device != x.device:
+            raise ValueError("value_out must be one float64 element on x's device")
+    _check(_lib.tvreg_tv_grad_noalloc(nx, ny, nz, prec, float(tau), _ptr(x, x.dtype, n, "x"),
+                                      _ptr(g, x.dtype, n, "grad") if grad else None,
+                                      ctypes.c_void_p(val.data_ptr()) if value else None,
+                                      _stream(x)), "tvreg_tv_grad_noalloc")
     return g, val
 
 

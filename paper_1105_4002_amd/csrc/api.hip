@@ -380,6 +380,93 @@ extern "C" tvreg_status tvreg_tv_grad(int32_t nx, int32_t ny, int32_t nz,
     return TVREG_OK;
 }
 
+// ------------------------------------------------ TV without an allocation
+// Per-block FP64 partial sums of tvreg_tv_grad_noalloc, [S_COUNT][blocks],
+// for at most NOALLOC_BLOCKS blocks of the TV grid.  Each device holds its own
+// copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress reports for the current device (the array's
+// name is a host-side stand-in there, not a device address).
+namespace {
+constexpr int NOALLOC_BLOCKS = 32768;  // 512^3 voxels: 8 x 128 x 32 blocks
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[NOALLOC_MAX_DEVICES];
+}  // namespace
+
+static __device__ __align__(256) double scratch[(size_t)S_COUNT * NOALLOC_BLOCKS];
+
+// Device address of `scratch` on the current device, looked up once per device.
+static tvreg_status scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(TVREG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(TVREG_EDEVICE, "device %d outside the %d the library tracks", dev,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TVREG_EDEVICE, "hipGetSymbolAddress(scratch): %s",
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return TVREG_OK;
+}
+
+extern "C" tvreg_status tvreg_tv_grad_noalloc(int32_t nx, int32_t ny, int32_t nz,
+                                              tvreg_precision precision, double tau,
+                                              const void *x, void *grad, double *tv_value,
+                                              void *stream)
+{
+    g_err.clear();
+    if (nx < 1 || ny < 1 || nz < 1)
+        return fail(TVREG_EINVAL, "sizes must be >= 1");
+    if ((int64_t)nx * ny * nz >= (int64_t(1) << 31))
+        return fail(TVREG_EINVAL, "volume larger than 2^31 entries");
+    if (!x || (!grad && !tv_value))
+        return fail(TVREG_EINVAL, "NULL input, or neither gradient nor value requested");
+    if (!(tau > 0) || !isfinite(tau))
+        return fail(TVREG_EINVAL, "tau must be positive and finite");
+    if (precision != TVREG_F32_RED64 && precision != TVREG_F64)
+        return fail(TVREG_EINVAL, "unknown precision %d", (int)precision);
+    const int pstride = max_reduce_blocks_vol(nx, ny, nz);
+    if (pstride > NOALLOC_BLOCKS)
+        return fail(TVREG_EINVAL,
+                    "volume %d x %d x %d needs %d TV blocks; the no-allocation scratch holds "
+                    "partial sums for at most %d (%zu bytes)",
+                    nx, ny, nz, pstride, NOALLOC_BLOCKS, sizeof(scratch));
+    double *part = nullptr;
+    if (tv_value) {
+        void *p = nullptr;
+        const tvreg_status s = scratch_address(&p);
+        if (s != TVREG_OK)
+            return s;
+        part = (double *)p;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int nb = 0;
+    if (precision == TVREG_F64)
+        TVR_HIP((launch_tv<double>(nx, ny, nz, tau, 1.0, (const double *)x, nullptr, nullptr,
+                                   (double *)grad, part, pstride, st, &nb)));
+    else
+        TVR_HIP((launch_tv<float>(nx, ny, nz, tau, 1.0, (const float *)x, nullptr, nullptr,
+                                  (float *)grad, part, pstride, st, &nb)));
+    if (tv_value) {
+        SlotList sl{};
+        sl.n = 1;
+        sl.slot[0] = S_TVY;
+        sl.count[0] = nb;
+        sl.dst[0] = tv_value;
+        TVR_HIP(launch_finalize(sl, part, pstride, st));
+    }
+    return TVREG_OK;
+}
+
 extern "C" tvreg_status tvreg_tv_hessvec(int32_t nx, int32_t ny, int32_t nz,
                                          tvreg_precision precision, double tau, const void *y,
                                          const void *v, void *out, double *grad_dot, void *ws,
