@@ -53,11 +53,23 @@ GP, GPBB, UPN, NESTEROV = 0, 1, 2, 3
 CONVERGED, NOTCONV, STALL = 0, 1, 2
 
 
+# TVREG_ORACLE_SANITIZE=1 selects a separate build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (CPU only; the process must preload libasan, see
+# the README); any report aborts the process.
+_SANITIZE = os.environ.get("TVREG_ORACLE_SANITIZE", "") == "1"
+if _SANITIZE:
+    _LIB_PATH = os.path.join(_HERE, "liboracle_san.so")
+
+
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (plain C, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+        flags = ["-O2"]
+        if _SANITIZE:
+            flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                     "-fno-sanitize-recover=all"]
+        cmd = ["gcc", *flags, "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
                "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB_PATH)
