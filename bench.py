@@ -13,18 +13,21 @@ A "step" is one UPN iteration: gradient at y (backprojection + TV stencil),
 projected trial step(s) with the projector's fused residual, the scalar
 control and the extrapolation.  `value` is gradient evaluations per second
 over exactly --steps iterations (inputs resident in HBM).  Beside it: the
-same rate with every operator on the fly, the time to a 1e-6 relative
-gradient-map tolerance from x0 = 0, the live per-kernel durations (HIP events
-around each launch of the timed solve), the dominant kernel's roofline, the
-32-problem batch and the differentiated 64^3 form, and the FP64 CPU oracle's
-gradient-evaluation rate on the host cores.
+same rate with every operator on the fly; the time to a 1e-6 relative
+gradient-map tolerance from x0 = 0 for UPN in FP32 and in FP64 (the metric's
+two halves, their ratio, and the FP32 result's distance to the FP64 one),
+and for GP in FP64 (the paper's plain method in plain precision; capped in
+wall time); the live per-kernel durations (HIP events around each launch of
+the timed solve) and the dominant kernel's roofline; the 32-problem batch,
+the differentiated 64^3 form and the paper's own 64^3 experiment; and the
+FP64 CPU oracle's gradient-evaluation rate on the host cores.
 
 Before the timed region the tile shapes of the on-the-fly operators are
 autotuned on the workload (the choice is reported), and a 1 GiB device copy
 measures the attainable HBM rate for the roofline.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--fp64] [--methods]
-                       [--gp64-iters N]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-paper]
+                       [--methods] [--gp64-iters N] [--gp64-seconds S]
 """
 from __future__ import annotations
 
@@ -40,36 +43,47 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 
-# HBM bytes per launch of the stored-A^T product, from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE scaled by a 1 GiB copy (profiles/cone256_kernels_hbm_traffic_pmc.md);
-# reported only while the product kernel's source (its block-size constant and
-# the body of spmv_voxels_block) is the one measured.
-MEASURED_TRAFFIC = {"kernel": "backproject", "source": "paper_1105_4002_amd/csrc/matrix.hip",
-                    "function": "spmv_voxels_block", "sha256_prefix": "625796131194bcb5",
-                    "bytes": 12.051e9 + 0.068e9}
+# HBM bytes per launch, from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) on the 256^3 cone workload, each scaled by what the counter reads
+# for a 1 GiB device copy (FETCH_SIZE 524308 KiB: x 2; WRITE_SIZE 1048576 KiB:
+# x 1).  An entry is reported only while the text of its source files is the
+# one measured, and the projector's only at the measured ray tile
+# (profiles/cone256_kernels_hbm_traffic_pmc.md).
+MEASURED_TRAFFIC = {
+    # project_kernel<float, cone, 64 columns, 4 waves>: 639945 + 25655.5 KiB
+    "project": {"sources": ["paper_1105_4002_amd/csrc/project.hip",
+                            "paper_1105_4002_amd/csrc/raywalk.hpp"],
+                "sha256_prefix": "37baf7e8b0c07c3f", "stored": None, "tile": (64, 4),
+                "bytes": (2 * 639945.0 + 25655.5) * 1024},
+    # spmv_sym_kernel<float, quarter turns, z mirror>: 814996.4 + 77781.3 KiB
+    "backproject": {"sources": ["paper_1105_4002_amd/csrc/matrix.hip"],
+                    "sha256_prefix": "80160ee1be1d8553", "stored": True, "tile": None,
+                    "bytes": (2 * 814996.4 + 77781.3) * 1024},
+}
 
 
-def kernel_source(path: str, function: str) -> str:
-    """The block-size constant and the text of `function` (signature to the
-    closing brace at column 0) in a HIP source file."""
-    text = open(path).read()
-    const = next(ln for ln in text.splitlines() if ln.startswith("constexpr int MB"))
-    start = text.index(f"void {function}(")
-    start = text.rindex("template", 0, start)
-    end = text.index("\n}\n", start) + 3
-    return const + "\n" + text[start:end]
-
-
-def measured_traffic(kernel: str, stored: bool):
+def sources_sha(paths) -> str:
     import hashlib
-    if not stored or kernel != MEASURED_TRAFFIC["kernel"]:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, stored: bool, tile=None):
+    """GB per launch measured for `kernel`, or None when there is no
+    measurement for this form of it (or its source has changed since)."""
+    e = MEASURED_TRAFFIC.get(kernel)
+    if e is None or (e["stored"] is not None and e["stored"] != stored):
         return None
-    src = kernel_source(os.path.join(ROOT, MEASURED_TRAFFIC["source"]),
-                        MEASURED_TRAFFIC["function"])
-    sha = hashlib.sha256(src.encode()).hexdigest()
-    if not sha.startswith(MEASURED_TRAFFIC["sha256_prefix"] or "-"):
+    if e["tile"] is not None and tuple(tile or ()) != e["tile"]:
         return None
-    return round(MEASURED_TRAFFIC["bytes"] / 1e9, 3)
+    if not sources_sha(e["sources"]).startswith(e["sha256_prefix"]):
+        return None
+    return round(e["bytes"] / 1e9, 3)
+
+
 FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed math)
 # vector instruction issue: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s
@@ -87,16 +101,20 @@ def log(msg: str) -> None:
 
 def kernel_model(name: str, N: int, m: int, nnz: int, es: int, stored: bool):
     """Algorithmic work of one launch of each solver kernel (es = bytes per
-    stored value).  Returns (bound, amount, unit, peak)."""
+    stored value).  Returns (bound, amount, unit, peak).
+
+    The two ray kernels are gathers: per non-zero a_ij one value of the other
+    vector is read (x for A, r for A^T), served by the caches or HBM.  The
+    projector walks its rays on the fly and is held by instruction issue: its
+    work is its vector instructions (PROJECT_VALU_PER_STEP per voxel step)
+    against the issue rate.  The backprojector streams the stored A^T; its
+    work is the gather model of the product, es per non-zero (the value of r
+    it reads) plus the volume written and the residual's compulsory read."""
     if name == "project":
-        # 7 flops per (ray, voxel) step of the walk: 3-way min, length,
-        # accumulate (FMA = 2), next-crossing update (FMA = 2)
-        return "alu", 7.0 * nnz, "TFLOP/s", FP64_VEC_PEAK
+        return "alu", PROJECT_VALU_PER_STEP * float(nnz), "T lane-instr/s", VALU_ISSUE_PEAK
     if name == "backproject":
         if stored:
-            # every non-zero streamed once (value + int32 ray index), r read
-            # once, the volume written once
-            return "hbm", (es + 4.0) * nnz + es * (m + N), "GB/s", HBM_PEAK
+            return "hbm", es * float(nnz) + 2.0 * es * N, "GB/s", HBM_PEAK
         # 10 flops per (voxel, ray) pair: two z-plane parameters (2 FMA),
         # max, min, length, |D| scale, accumulate (FMA)
         return "alu", 10.0 * nnz, "TFLOP/s", FP64_VEC_PEAK
@@ -230,13 +248,14 @@ def grad_eval_graph(tv, torch, G, b, x, w, n: int = 100, runs: int = 5) -> dict:
 
 
 def gp64_leg(tv, torch, G, b, common: dict, tol: float, max_iter: int, stored: bool,
-             chunk: int = 4000) -> dict:
+             chunk: int = 4000, max_seconds: float = 0.0) -> dict:
     """GP (eq. 6 with BT) in FP64 to the relative gradient-map tolerance, in
     chunks of `chunk` iterations so that progress is reported.  GP's only
     state is (x, L): a chunk starts from the previous chunk's x with L_bar =
     its last L and stops on |G| <= tol |G_0| written as the absolute test
     |G| / N <= tol |G_0| / N, so the chunks take exactly the steps of one
-    uninterrupted run."""
+    uninterrupted run.  With max_seconds > 0 no chunk starts after that much
+    wall time (the result then says not converged, with the |G| reached)."""
     if stored:
         G.attach_matrix()
     ws = tv.solve_workspace(G, tv.GP)
@@ -259,6 +278,8 @@ def gp64_leg(tv, torch, G, b, common: dict, tol: float, max_iter: int, stored: b
             f"{time.perf_counter() - s0:.1f} s")
         if status != tv.ENOTCONV:
             break
+        if max_seconds > 0 and time.perf_counter() - s0 >= max_seconds:
+            break
     torch.cuda.synchronize()
     dt = time.perf_counter() - s0
     if stored:
@@ -268,10 +289,13 @@ def gp64_leg(tv, torch, G, b, common: dict, tol: float, max_iter: int, stored: b
 
 
 def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool,
-              stored: bool = False):
+              stored: bool = False, tune: bool = True, probe_iters: int = 100):
     """The 32-problem batch (uneven sizes, views and alphas), FP32 UPN to tol:
     one tvreg_solve_batched call, and optionally the same problems one by one;
-    with `stored`, every problem streams its stored A^T (built beforehand)."""
+    with `stored`, every problem streams its stored A^T (built beforehand).
+    With `tune`, the tile shapes are chosen first (outside the timing): each
+    problem's own autotuned shapes or the defaults, whichever runs the first
+    `probe_iters` rounds of the batch faster."""
     ws_ = synth.cfg_batch()
     geoms, bs = [], []
     for w in ws_:
@@ -292,6 +316,40 @@ def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool
     params = [dict(method=tv.UPN, alpha=w.alpha, tau=w.tau, eps=tol, max_iter=max_iter)
               for w in ws_]
     ws = tv.solve_batched_workspace(geoms, dev)
+    tuned = None
+    if tune:
+        # Shapes are chosen for the batch as a whole: every problem's shapes
+        # from its own autotune (timed alone), against the default shapes
+        # for all, each timed over the first rounds of this batch.
+        defaults = [G.tuning for G in geoms]
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        own = []
+        for G in geoms:
+            G.autotune(reps=3)
+            own.append(G.tuning)
+        probe = [dict(p, eps=0.0, max_iter=probe_iters) for p in params]
+
+        def rounds_s(shapes):
+            for G, sh in zip(geoms, shapes):
+                G.set_tuning(*sh)
+            tv.solve_batched(geoms, bs, probe, workspace=ws)
+            torch.cuda.synchronize()
+            r0 = time.perf_counter()
+            tv.solve_batched(geoms, bs, probe, workspace=ws)
+            torch.cuda.synchronize()
+            return time.perf_counter() - r0
+
+        t_own, t_def = rounds_s(own), rounds_s(defaults)
+        pick = own if t_own < t_def else defaults
+        for G, sh in zip(geoms, pick):
+            G.set_tuning(*sh)
+        torch.cuda.synchronize()
+        tuned = {"seconds": round(time.perf_counter() - a0, 3), "probe_rounds": probe_iters,
+                 "per_problem_shapes_s": round(t_own, 4), "default_shapes_s": round(t_def, 4),
+                 "chosen": "per_problem" if pick is own else "default",
+                 "distinct_shapes": len(set(pick))}
+    ws = tv.solve_batched_workspace(geoms, dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     xs, infos, status = tv.solve_batched(geoms, bs, params, workspace=ws)
@@ -301,7 +359,8 @@ def batch_leg(tv, synth, torch, dev, tol: float, max_iter: int, sequential: bool
            "batched_seconds": round(dt, 3), "status": int(status),
            "iters_max": max(i["iters"] for i in infos),
            "grad_evals": int(sum(i["grad_evals"] for i in infos)),
-           "converged": int(sum(1 for i in infos if i["stop_reason"] == tv.OK))}
+           "converged": int(sum(1 for i in infos if i["stop_reason"] == tv.OK)),
+           "shapes": tuned}
     if stored:
         out["stored_transpose_gib"] = round(sum(G.matrix_bytes for G in geoms) / 2**30, 3)
         out["stored_transpose_build_s"] = build_s
@@ -452,10 +511,13 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=5000)
     ap.add_argument("--no-tol", action="store_true", help="skip the time-to-tolerance solve")
-    ap.add_argument("--fp64", action="store_true", help="also time UPN in FP64 to tolerance")
-    ap.add_argument("--gp64-iters", type=int, default=0,
-                    help="also run GP in FP64 to --tol (chunks of 4000 iterations, at most "
-                         "this many)")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 UPN solve to tolerance (the metric's FP64 half)")
+    ap.add_argument("--gp64-iters", type=int, default=100000,
+                    help="GP in FP64 to --tol: at most this many iterations (0: skip)")
+    ap.add_argument("--gp64-seconds", type=float, default=280.0,
+                    help="GP in FP64: start no chunk of 4000 iterations after this many "
+                         "seconds (0: no limit)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-matrix", action="store_true",
                     help="evaluate A^T on the fly in the headline solve")
@@ -478,8 +540,8 @@ def main() -> int:
                     help="CPU only: time the FP64 oracle on every workload, on all host threads "
                          "and (in a child process) on one, and print that table instead")
     ap.add_argument("--oracle-evals-only", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--paper", action="store_true",
-                    help="also run the paper's 64^3 experiment (55 and 19 sphere views)")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper's 64^3 experiment (55 and 19 sphere views)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -545,7 +607,8 @@ def main() -> int:
         mnnz = G32.attach_matrix()
         torch.cuda.synchronize()
         matrix = {"gib": round(G32.matrix_bytes / 2**30, 3), "nnz": mnnz,
-                  "build_s": round(time.perf_counter() - m0, 3)}
+                  "build_s": round(time.perf_counter() - m0, 3),
+                  "voxels_per_entry": G32.symmetry, "stored_bytes": G32.matrix_bytes}
 
     copy_gbs = copy_bandwidth(torch, dev)
     log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
@@ -596,22 +659,42 @@ def main() -> int:
                              "total_ms": round(ms, 3), "bound": bound,
                              "frac": round(amount / avg / peak, 4)}
             if name == "project":
-                # the walk's instruction stream against the chip's issue rate
-                kernels[name]["valu_issue_frac"] = round(
-                    PROJECT_VALU_PER_STEP * nnz / avg / VALU_ISSUE_PEAK, 4)
+                # beside the issue rate: 7 flops per voxel step (3-way min,
+                # length, two FMAs) against the FP64 vector peak, and the
+                # gather model (4 B per non-zero + the residual's 8 B per ray)
+                kernels[name]["flop_frac"] = round(7.0 * nnz / avg / FP64_VEC_PEAK, 4)
+                kernels[name]["gather_model_hbm_frac"] = round(
+                    (4.0 * nnz + 8.0 * m) / avg / HBM_PEAK, 4)
+            if name == "backproject" and stored and matrix:
+                # the stored layout's own stream: value + key per stored
+                # entry (padding included), r, the volume
+                lay = matrix["stored_bytes"] + 4.0 * (m + N)
+                kernels[name]["stored_layout_GBps"] = round(lay / avg / 1e9, 1)
+                kernels[name]["compulsory_hbm_frac"] = round(4.0 * (m + 2 * N) / avg / HBM_PEAK, 4)
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     bound, amount, unit, peak = kernel_model(dom, N, m, nnz, 4, stored)
     avg_s = kernels[dom]["avg_ms"] / 1e3
-    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    scale = 1e9 if unit == "GB/s" else 1e12
+    tile = G32.tuning[:2]
     roofline = {"kernel": dom, "bound": bound, "achieved": round(amount / avg_s / scale, 3),
                 "peak": peak / scale, "unit": unit, "frac": round(amount / avg_s / peak, 4),
-                "traffic": measured_traffic(dom, stored)}
+                "traffic": measured_traffic(dom, stored, tile)}
     if bound == "hbm":
         roofline["copy_peak"] = round(copy_gbs, 1)
         roofline["frac_of_copy"] = round(amount / avg_s / 1e9 / copy_gbs, 4)
     if roofline["traffic"] is not None:
         roofline["traffic_unit"] = "GB per launch"
-        roofline["algorithmic"] = round(amount / 1e9, 3)
+        # the bytes the kernel must move: its own model for an HBM-bound
+        # kernel; for the projector the gather model (4 B per non-zero, the
+        # residual's 8 B per ray)
+        roofline["algorithmic_GB"] = round(
+            (amount if bound == "hbm" else 4.0 * nnz + 8.0 * m) / 1e9, 3)
+    for name in ("project", "backproject"):
+        if name in kernels:
+            t_gb = measured_traffic(name, stored, tile)
+            if t_gb is not None:
+                kernels[name]["traffic_GB"] = t_gb
+                kernels[name]["traffic_GBps"] = round(t_gb / (kernels[name]["avg_ms"] / 1e3), 1)
 
     result = {
         "metric": "gradient evals/sec + time to 1e-6 gradient-map tol, 256^3 UPN FP32 vs FP64",
@@ -655,8 +738,9 @@ def main() -> int:
                                 "ms_per_step": round(1e3 * d0 / args.steps, 4)}
         G32.attach_matrix()
 
+    x_tol = {}
     if not args.no_tol:
-        for label, G, bb in [("f32", G32, b32)] + ([("f64", G64, b64)] if args.fp64 else []):
+        for label, G, bb in [("f32", G32, b32)] + ([] if args.no_fp64 else [("f64", G64, b64)]):
             log(f"time to tolerance {args.tol:g}: UPN {label}")
             if label == "f64" and stored:
                 G.attach_matrix()
@@ -673,17 +757,29 @@ def main() -> int:
                 "gm_rel": info["gm_rel"], "status": info["stop_reason"],
                 "grad_evals_per_s": round(info["grad_evals"] / dt, 3)}
             log(f"  {dt:.2f} s, {info['iters']} iterations, status {info['stop_reason']}")
+            x_tol[label] = xs.double()
             if label == "f64":
                 del ws
                 if stored:
                     G.detach_matrix()
+        if "f64" in x_tol:
+            # the FP32 result against the FP64 one at the same tolerance: the
+            # precision's share of the error (both carry the tolerance's)
+            d = x_tol["f32"] - x_tol["f64"]
+            result["time_to_tol_upn_f32"]["vs_f64"] = {
+                "rel_l2": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(x_tol["f64"])),
+                "max_abs": float(d.abs().max())}
+            result["ratios"] = {"upn_f64_over_upn_f32_seconds": round(
+                result["time_to_tol_upn_f64"]["seconds"] / result["time_to_tol_upn_f32"]["seconds"], 3)}
+        x_tol.clear()
     if not args.no_legs:
         log("32-problem batch, FP32 UPN to 1e-6")
-        result["batch32"] = batch_leg(tv, synth, torch, dev, 1e-6, 5000, args.batch_seq)
+        result["batch32"] = batch_leg(tv, synth, torch, dev, 1e-6, 5000, args.batch_seq,
+                                      tune=not args.no_tune)
         log(f"  {result['batch32']}")
         log("32-problem batch with stored A^T, FP32 UPN to 1e-6")
         result["batch32_stored"] = batch_leg(tv, synth, torch, dev, 1e-6, 5000, args.batch_seq,
-                                             stored=True)
+                                             stored=True, tune=not args.no_tune)
         log(f"  {result['batch32_stored']}")
         log("differentiated form: 64^3, K = 30")
         result["unrolled64"] = unrolled_leg(tv, synth, torch, dev)
@@ -712,7 +808,7 @@ def main() -> int:
     if args.small:
         log(f"small workloads: gradient evals/s and time to {args.tol:g}")
         result["small"] = small_leg(tv, synth, torch, dev, args.tol)
-    if args.paper:
+    if not args.no_paper:
         log("the paper's experiment: 64^3, 55 and 19 views over the sphere, GP/GPBB/UPN FP64")
         result["paper_experiment"] = paper_leg(tv, synth, torch, dev)
         log(f"  {result['paper_experiment']}")
@@ -720,9 +816,9 @@ def main() -> int:
         log(f"GP FP64 (the paper's plain method, plain precision) to {args.tol:g}, "
             f"at most {args.gp64_iters} iterations")
         result["gp_f64"] = gp64_leg(tv, torch, G64, b64, common, args.tol, args.gp64_iters,
-                                    stored)
+                                    stored, max_seconds=args.gp64_seconds)
         if "time_to_tol_upn_f32" in result and result["gp_f64"]["status"] == tv.OK:
-            result["gp_f64"]["ratio_to_upn_f32"] = round(
+            result.setdefault("ratios", {})["gp_f64_over_upn_f32_seconds"] = round(
                 result["gp_f64"]["seconds"] / result["time_to_tol_upn_f32"]["seconds"], 2)
 
     if not args.no_cpu:

@@ -131,9 +131,38 @@ tvreg_status tvreg_backproject(const tvreg_geometry *geom, const void *r_dev, vo
  * until tvreg_matrix_detach or tvreg_destroy_geometry) and switches the
  * geometry's backprojector to it; it synchronises `stream`.  Neither may run
  * while another call uses the geometry.  Size: about (sizeof(T) + 4) bytes
- * per non-zero plus slice padding (1.3e9 non-zeros, 12 GiB in FP32, for a
- * 256^3 cone-beam scan of 60 views at 384 x 256).
+ * per stored entry plus slice padding (1.3e9 non-zeros, 12 GiB in FP32, for
+ * a 256^3 cone-beam scan of 60 views at 384 x 256; 1.4 GiB when the scan's
+ * symmetry is used, see below).
  */
+/*
+ * Symmetric storage.  A circular cone scan whose views are evenly spaced
+ * over the full circle maps onto itself under turns of the volume about z:
+ * with V divisible by 4 and a square volume of even side, turning by a
+ * quarter carries ray (view v, row, col) onto ray (v + V/4, row, col) and
+ * voxel (i, j, k) onto (nx - 1 - j, i, k), so both have the same length (V
+ * even, ny even: the half turn, v + V/2 and (nx - 1 - i, ny - 1 - j)); with
+ * nz even the mirror z -> -z carries row r onto rows - 1 - r and k onto
+ * nz - 1 - k.  The stored transpose of such a geometry keeps only the voxels
+ * of one cell of that group (a quadrant of the plane times the lower half in
+ * z: one eighth of the entries for the 256^3 scan of 60 views) and its
+ * product applies every entry to all images of its voxel.  The lengths of
+ * the images are those of the stored voxel's rays: equal to the ones the
+ * projector computes for the image rays up to the rounding of the view
+ * angles' cosines (about 1e-16 relative before the rounding to T).  Used only
+ * for the cone beam with an even detector in both directions (no ray runs
+ * inside a voxel face), view directions matching the turn to 1e-12, and
+ * views, rows and columns that pack into 31 bits.  On by default.
+ * tvreg_set_symmetry(geom, 0) keeps every voxel (the plain layout), 1 uses
+ * the symmetry again; it must precede tvreg_matrix_plan / attach (EINVAL
+ * while a transpose is attached).  tvreg_matrix_symmetry returns the number
+ * of voxels one stored entry serves (1, 2, 4 or 8) for the attached
+ * transpose or, before attaching, for the one tvreg_matrix_attach would
+ * build.
+ */
+tvreg_status tvreg_set_symmetry(tvreg_geometry *geom, int32_t use);
+int32_t tvreg_matrix_symmetry(const tvreg_geometry *geom);
+
 size_t tvreg_matrix_scratch_bytes(const tvreg_geometry *geom);
 tvreg_status tvreg_matrix_plan(const tvreg_geometry *geom, void *scratch_dev, size_t scratch_bytes,
                                size_t *matrix_bytes, int64_t *nnz, void *stream);
@@ -158,8 +187,9 @@ tvreg_status tvreg_matrix_detach(tvreg_geometry *geom);
  * events on `stream`), keeps the fastest of each operator in the geometry
  * and reports all timings; it synchronises `stream` and must not run while
  * another call uses the geometry.  The backprojector is timed on the fly
- * even when a stored transpose is attached.  tvreg_solve_batched always
- * uses the default shapes.
+ * even when a stored transpose is attached.  tvreg_solve_batched runs every
+ * problem with its own geometry's shapes, except a backprojector depth of 16,
+ * which it runs at 8 (every depth gives bitwise the same result).
  */
 typedef struct {
     int32_t project_tile_cols;

@@ -72,7 +72,8 @@ class _SolveInfo(ctypes.Structure):
 # Every symbol include/tvreg.h declares.
 EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
            "tvreg_backproject", "tvreg_matrix_scratch_bytes", "tvreg_matrix_plan",
-           "tvreg_matrix_attach", "tvreg_matrix_detach", "tvreg_autotune_workspace_bytes",
+           "tvreg_matrix_attach", "tvreg_matrix_detach", "tvreg_set_symmetry",
+           "tvreg_matrix_symmetry", "tvreg_autotune_workspace_bytes",
            "tvreg_autotune", "tvreg_get_tuning", "tvreg_set_tuning", "tvreg_tv_workspace_bytes",
            "tvreg_tv_grad", "tvreg_tv_grad_noalloc", "tvreg_tv_hessvec",
            "tvreg_objective_workspace_bytes", "tvreg_objective_grad",
@@ -109,6 +110,10 @@ def _load():
     L.tvreg_matrix_attach.restype = st
     L.tvreg_matrix_detach.argtypes = [vp]
     L.tvreg_matrix_detach.restype = st
+    L.tvreg_set_symmetry.argtypes = [vp, ctypes.c_int32]
+    L.tvreg_set_symmetry.restype = st
+    L.tvreg_matrix_symmetry.argtypes = [vp]
+    L.tvreg_matrix_symmetry.restype = ctypes.c_int32
     L.tvreg_autotune_workspace_bytes.argtypes = [vp]
     L.tvreg_autotune_workspace_bytes.restype = sz
     L.tvreg_autotune.argtypes = [vp, vp, sz, ctypes.c_int32, ctypes.POINTER(_Tuning), vp]
@@ -241,9 +246,19 @@ class Geometry:
             lib_.tvreg_destroy_geometry(h)
             self.handle = None
 
-    def attach_matrix(self, device="cuda") -> int:
+    def set_symmetry(self, use: bool) -> None:
+        """Whether a stored transpose uses the scan's symmetry
+        (tvreg_set_symmetry; on by default).  Not while a matrix is attached."""
+        _check(_lib.tvreg_set_symmetry(self.handle, 1 if use else 0), "tvreg_set_symmetry")
+
+    def attach_matrix(self, device="cuda", symmetric: bool = True) -> int:
         """Builds the stored system matrix (tvreg_matrix_plan / _attach) in a
-        torch allocation the geometry keeps; returns the number of non-zeros."""
+        torch allocation the geometry keeps; returns the number of non-zeros
+        of A.  With symmetric (the default) a circular cone scan that maps
+        onto itself under turns and the z mirror stores one cell of voxels
+        (symmetric=False: every voxel).  `symmetry` then holds the voxels one
+        stored entry serves."""
+        self.set_symmetry(symmetric)
         scratch = torch.empty(_lib.tvreg_matrix_scratch_bytes(self.handle), dtype=torch.uint8,
                               device=device)
         nbytes = ctypes.c_size_t(0)
@@ -258,11 +273,13 @@ class Geometry:
                                         buf.numel(), stream), "tvreg_matrix_attach")
         self._matrix = buf
         self.nnz = int(nnz.value)
+        self.symmetry = int(_lib.tvreg_matrix_symmetry(self.handle))
         return self.nnz
 
     def detach_matrix(self) -> None:
         _check(_lib.tvreg_matrix_detach(self.handle), "tvreg_matrix_detach")
         self._matrix = None
+        self.symmetry = 0
 
     @property
     def matrix_bytes(self) -> int:

@@ -75,6 +75,38 @@ extern "C" const char *tvreg_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char *tvreg_version(void) { return "tvreg-gfx950 0.1.0"; }
 
+// The symmetry group of a scan that a stored transpose uses (see MatDev):
+// turns about z and the z mirror.  A circular cone scan qualifies when view
+// v + V/4 (V/2) is view v turned by a quarter (half) turn, to 1e-12 in its
+// direction cosines; the detector must be even in both directions, so that
+// no ray runs inside a voxel face (the half-open cells are not symmetric
+// under a turn or a mirror).  Quarter turns need a square volume of even
+// side, half turns an even ny, the mirror an even nz.
+static void scan_symmetry(const tvreg_geometry_desc &d, const double *angles, int &rot, int &mir)
+{
+    rot = 1;
+    mir = 0;
+    if (d.beam != TVREG_CONE || d.det_cols % 2 || d.det_rows % 2)
+        return;
+    const int V = d.n_views;
+    auto turned = [&](int step, double ang) {  // view (v + step) % V = view v turned by ang
+        const double ca = cos(ang), sa = sin(ang);
+        for (int v = 0; v < V; ++v) {
+            const double a = angles[v], b = angles[(v + step) % V];
+            const double c = cos(a), s = sin(a);
+            if (fabs(cos(b) - (c * ca - s * sa)) > 1e-12 || fabs(sin(b) - (c * sa + s * ca)) > 1e-12)
+                return false;
+        }
+        return true;
+    };
+    if (d.nx == d.ny && d.nx % 2 == 0 && V % 4 == 0 && turned(V / 4, 0.5 * M_PI))
+        rot = 4;
+    else if (d.ny % 2 == 0 && V % 2 == 0 && turned(V / 2, M_PI))
+        rot = 2;
+    if (d.nz % 2 == 0)
+        mir = 1;
+}
+
 extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
                                               tvreg_precision precision, tvreg_geometry **out)
 {
@@ -281,6 +313,7 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     for (int row = 0; cone && row < Rw; ++row)
         if (rowt[row].invDz == 0.0)
             g.flat_row = row;
+    scan_symmetry(G->desc, G->angles.data(), g.sym_rot, g.sym_mir);
     // partial sums sized for every projector tile shape the tuner may pick
     G->pstride = std::max({project_blocks_max(g), max_reduce_blocks_vol(g.nx, g.ny, g.nz),
                            elementwise_blocks(N), elementwise_blocks(m)});
@@ -1077,11 +1110,51 @@ struct MatLayout {
     size_t off_v, w_v, cnt_v, val_v, idx_v, total;
 };
 
+// The cell of voxels a stored transpose keeps (see MatDev): one cell of the
+// symmetry group the geometry uses (scan_symmetry), when the packed ray key
+// of the layout fits 31 bits; otherwise every voxel.
+MatDev mat_cell(const tvreg_geometry *G)
+{
+    const tvreg_geometry_desc &d = G->desc;
+    MatDev M{};
+    M.rot = 1;
+    M.mx = d.nx;
+    M.my = d.ny;
+    M.mz = d.nz;
+    auto bits = [](int n) {
+        int b = 0;
+        while ((1 << b) < n)
+            ++b;
+        return b;
+    };
+    const int kc = bits(d.det_cols), kr = bits(d.det_rows), kv = bits(d.n_views);
+    if ((G->g.sym_rot <= 1 && !G->g.sym_mir) || kc + kr + kv > 31)
+        return M;
+    if (G->g.sym_rot == 4) {
+        M.rot = 4;
+        M.mx = d.nx / 2;
+        M.my = d.ny / 2;
+    } else if (G->g.sym_rot == 2) {
+        M.rot = 2;
+        M.my = d.ny / 2;
+    }
+    if (G->g.sym_mir) {
+        M.mir = 1;
+        M.mz = d.nz / 2;
+    }
+    M.kc = kc;
+    M.kr = kr;
+    return M;
+}
+
+int mat_order(const MatDev &M) { return M.rot * (M.mir ? 2 : 1); }
+
 // fixed part (slice table and counts), then the entries once counted
 MatLayout mat_layout(const tvreg_geometry *G, int64_t ev)
 {
+    const MatDev C = mat_cell(G);
     MatLayout L{};
-    L.sv = mat_slices(G->g.nx, G->g.ny, G->g.nz);
+    L.sv = mat_slices(C.mx, C.my, C.mz);
     L.ev = ev;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1091,7 +1164,7 @@ MatLayout mat_layout(const tvreg_geometry *G, int64_t ev)
     };
     L.off_v = take(sizeof(int64_t) * (size_t)L.sv);
     L.w_v = take(sizeof(int32_t) * (size_t)L.sv);
-    L.cnt_v = take(sizeof(int32_t) * (size_t)G->N);
+    L.cnt_v = take(sizeof(int32_t) * (size_t)C.mx * C.my * C.mz);
     L.val_v = take(elem_size(G->prec) * (size_t)ev);
     L.idx_v = take(sizeof(int32_t) * (size_t)ev);
     L.total = off;
@@ -1104,15 +1177,16 @@ tvreg_status count_entries(const tvreg_geometry *G, int32_t *cnt_v, int32_t *w_v
                            std::vector<int64_t> &off_v, int64_t &ev, int64_t *nnz)
 {
     GeomDev g = G->g;
-    g.mat = MatDev{};
-    const int64_t sv = mat_slices(g.nx, g.ny, g.nz);
+    g.mat = mat_cell(G);
+    const int64_t sv = mat_slices(g.mat.mx, g.mat.my, g.mat.mz);
+    const size_t ncell = (size_t)g.mat.mx * g.mat.my * g.mat.mz;
     TVR_HIP(launch_matrix_count(g, cnt_v, st));
     TVR_HIP(launch_slice_widths(g, cnt_v, w_v, st));
     std::vector<int32_t> wv((size_t)sv);
     TVR_HIP(hipMemcpyAsync(wv.data(), w_v, sizeof(int32_t) * wv.size(), hipMemcpyDeviceToHost, st));
     std::vector<int32_t> cv;
     if (nnz) {
-        cv.resize((size_t)G->N);
+        cv.resize(ncell);
         TVR_HIP(hipMemcpyAsync(cv.data(), cnt_v, sizeof(int32_t) * cv.size(),
                                hipMemcpyDeviceToHost, st));
     }
@@ -1127,7 +1201,7 @@ tvreg_status count_entries(const tvreg_geometry *G, int32_t *cnt_v, int32_t *w_v
         int64_t t = 0;
         for (int32_t c : cv)
             t += c;
-        *nnz = t;
+        *nnz = t * mat_order(g.mat);  // every stored entry stands for its images
     }
     return TVREG_OK;
 }
@@ -1187,7 +1261,7 @@ extern "C" tvreg_status tvreg_matrix_attach(tvreg_geometry *G, void *matrix, siz
         return fail(TVREG_ENOMEM, "matrix of %zu bytes needed", L.total);
     TVR_HIP(hipMemcpyAsync(b + L.off_v, off_v.data(), sizeof(int64_t) * off_v.size(),
                            hipMemcpyHostToDevice, st));
-    MatDev M{};
+    MatDev M = mat_cell(G);
     M.present = 1;
     M.sv = L.sv;
     M.off_v = (const int64_t *)(b + L.off_v);
@@ -1215,6 +1289,29 @@ extern "C" tvreg_status tvreg_matrix_detach(tvreg_geometry *G)
         return fail(TVREG_EINVAL, "NULL geometry");
     G->g.mat = MatDev{};
     return TVREG_OK;
+}
+
+extern "C" tvreg_status tvreg_set_symmetry(tvreg_geometry *G, int32_t use)
+{
+    g_err.clear();
+    if (!G || (use != 0 && use != 1))
+        return fail(TVREG_EINVAL, "NULL geometry or use not 0 / 1");
+    if (G->g.mat.present)
+        return fail(TVREG_EINVAL, "detach the stored transpose first");
+    G->sym_off = use ? 0 : 1;
+    int rot = 1, mir = 0;
+    if (use)
+        scan_symmetry(G->desc, G->angles.data(), rot, mir);
+    G->g.sym_rot = rot;
+    G->g.sym_mir = mir;
+    return TVREG_OK;
+}
+
+extern "C" int32_t tvreg_matrix_symmetry(const tvreg_geometry *G)
+{
+    if (!G)
+        return 0;
+    return mat_order(G->g.mat.present ? G->g.mat : mat_cell(G));
 }
 
 extern "C" void tvreg_profile_enable(int32_t on)

@@ -302,7 +302,23 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_kernel(GeomDev g,
 }
 
 // Batched: G = A^T RY for every problem whose gradient is due this round.
-template <typename T>
+template <typename T, int CZ>
+__device__ __forceinline__ void backproject_grouped_body(const BatchProblem<T> &P, int local,
+                                                         Tile &tile)
+{
+    const int gx = (P.g.nx + BP_TX - 1) / BP_TX, gy = (P.g.ny + BP_TY - 1) / BP_TY;
+    const int bx = local % gx, by = (local / gx) % gy, bz = local / (gx * gy);
+    if (P.g.beam3d)  // block-uniform
+        backproject_block3d<T, CZ>(P.g, P.RY, P.G, bx, by, bz);
+    else if (P.g.cone)
+        backproject_block<T, true, CZ>(P.g, P.RY, P.G, bx, by, bz, tile);
+    else
+        backproject_block<T, false, CZ>(P.g, P.RY, P.G, bx, by, bz, tile);
+}
+
+// One kernel per voxel depth CZ (4 or 8): a depth chosen per problem inside
+// one kernel would size every block's registers for the deepest variant.
+template <typename T, int CZ>
 __global__ __launch_bounds__(BP_THREADS) void backproject_grouped(BatchProblem<T> *probs,
                                                                  const int *offs, int n)
 {
@@ -311,40 +327,37 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_grouped(BatchProblem<T
     const BatchProblem<T> &P = probs[p];
     if (P.state != B_RUNNING || !P.need_grad)
         return;
-    const int local = blockIdx.x - offs[p];
-    constexpr int BP_CZ = BP_CZ_DEFAULT;
-    const int gx = (P.g.nx + BP_TX - 1) / BP_TX, gy = (P.g.ny + BP_TY - 1) / BP_TY;
-    const int bx = local % gx, by = (local / gx) % gy, bz = local / (gx * gy);
-    if (P.g.beam3d)  // block-uniform
-        backproject_block3d<T, BP_CZ>(P.g, P.RY, P.G, bx, by, bz);
-    else if (P.g.cone)
-        backproject_block<T, true, BP_CZ>(P.g, P.RY, P.G, bx, by, bz, tile);
-    else
-        backproject_block<T, false, BP_CZ>(P.g, P.RY, P.G, bx, by, bz, tile);
+    backproject_grouped_body<T, CZ>(P, blockIdx.x - offs[p], tile);
 }
 
 }  // namespace
 
-// blocks of the grouped (default-shape) backprojector
+int backproject_depth(const GeomDev &g) { return g.bp_cz == 4 || g.bp_cz == 16 ? g.bp_cz : 8; }
+
+// blocks of the backprojector at the geometry's voxel depth
 int backproject_blocks(const GeomDev &g)
 {
-    return ((g.nx + BP_TX - 1) / BP_TX) * ((g.ny + BP_TY - 1) / BP_TY) *
-           ((g.nz + BP_CZ_DEFAULT - 1) / BP_CZ_DEFAULT);
+    const int cz = backproject_depth(g);
+    return ((g.nx + BP_TX - 1) / BP_TX) * ((g.ny + BP_TY - 1) / BP_TY) * ((g.nz + cz - 1) / cz);
 }
 
 template <typename T>
 hipError_t launch_backproject_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
-                                      hipStream_t st)
+                                      int depth, hipStream_t st)
 {
-    hipLaunchKernelGGL((backproject_grouped<T>), dim3(blocks), dim3(BP_THREADS), 0, st, probs,
-                       offs, n);
+    if (depth == 4)
+        hipLaunchKernelGGL((backproject_grouped<T, 4>), dim3(blocks), dim3(BP_THREADS), 0, st,
+                           probs, offs, n);
+    else
+        hipLaunchKernelGGL((backproject_grouped<T, 8>), dim3(blocks), dim3(BP_THREADS), 0, st,
+                           probs, offs, n);
     return hipGetLastError();
 }
 
 template hipError_t launch_backproject_grouped<float>(BatchProblem<float> *, const int *, int,
-                                                      int, hipStream_t);
+                                                      int, int, hipStream_t);
 template hipError_t launch_backproject_grouped<double>(BatchProblem<double> *, const int *, int,
-                                                       int, hipStream_t);
+                                                       int, int, hipStream_t);
 
 template <typename T, int CZ>
 static void launch_backproject_cz(const GeomDev &g, const T *r, T *out, hipStream_t st)

@@ -155,7 +155,13 @@ template hipError_t launch_control_batched<double>(BatchProblem<double> *, int, 
 namespace {
 
 // Kernel families of a round, each with its own prefix table of block counts.
-enum Family : int { F_BP = 0, F_SP, F_VOX, F_TR, F_PJ, F_EX, F_COUNT };
+// The on-the-fly backprojector has one family per voxel depth (F_BP4 ..
+// F_BP8) and the projector one per block shape (waves per block, 1, 2, 4 or
+// 8: F_PJ1 .. F_PJ8), so that every problem runs its own tuned tiles, each
+// family in a kernel compiled for that shape alone.
+enum Family : int { F_BP4 = 0, F_BP8, F_SP, F_VOX, F_TR, F_PJ1, F_PJ2, F_PJ4, F_PJ8, F_EX, F_COUNT };
+constexpr int BP_FAMILY_CZ[2] = {4, 8};
+constexpr int PJ_FAMILY_TY[4] = {1, 2, 4, 8};
 
 // Per-problem region: X, XB, YB, G, XT (N values each), RX, RXB, RYB (m
 // each), the partial-sum slots and the finalised sums.
@@ -196,31 +202,36 @@ size_t batch_bytes(int n, const tvreg_geometry *const *geoms, std::vector<size_t
     return off;
 }
 
-// grouped launches use the default tile shapes whatever the geometry's tuning
-// (a stored transpose, when attached, is used)
-GeomDev default_shapes(const GeomDev &g0)
+// waves per projector block of a geometry's ray tile (the tuner's values)
+int pj_waves(const GeomDev &g) { return g.pj_ty == 1 || g.pj_ty == 2 || g.pj_ty == 8 ? g.pj_ty : 4; }
+
+// Grouped launches run every problem with its geometry's tile shapes (and its
+// stored transpose, when attached), except a backprojector depth of 16, which
+// runs at 8: the grouped kernel at depth 16 needs 256 registers per lane, one
+// wave per SIMD.
+GeomDev batch_shapes(const GeomDev &g0)
 {
     GeomDev g = g0;
-    g.pj_wc = PJ_WC_DEFAULT;
-    g.pj_ty = PJ_TY_DEFAULT;
-    g.bp_cz = BP_CZ_DEFAULT;
+    g.bp_cz = backproject_depth(g0) == 4 ? 4 : 8;
     return g;
 }
 
 int family_blocks(const tvreg_geometry *G, int f)
 {
-    const GeomDev g = default_shapes(G->g);
+    const GeomDev g = batch_shapes(G->g);
+    if (f >= F_PJ1 && f <= F_PJ8)
+        return pj_waves(g) == PJ_FAMILY_TY[f - F_PJ1] ? project_blocks(g) : 0;
+    if (f >= F_BP4 && f <= F_BP8)
+        return !g.mat.present && backproject_depth(g) == BP_FAMILY_CZ[f - F_BP4]
+                   ? backproject_blocks(g)
+                   : 0;
     switch (f) {
-    case F_BP:
-        return g.mat.present ? 0 : backproject_blocks(g);
     case F_SP:
         return g.mat.present ? matrix_product_blocks(g) : 0;
     case F_VOX:
         return max_reduce_blocks_vol(g.nx, g.ny, g.nz);
     case F_TR:
         return transpose_blocks(g.nx, g.ny, g.nz);
-    case F_PJ:
-        return project_blocks(g);
     default:
         return elementwise_blocks(G->N) + elementwise_blocks(G->m);
     }
@@ -266,7 +277,7 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         char *r = ws + base[i];
         BatchProblem<T> &P = hp[i];
         memset(&P, 0, sizeof(P));
-        P.g = default_shapes(G->g);
+        P.g = batch_shapes(G->g);
         P.N = (int)G->N;
         P.m = (int)G->m;
         P.nb_vox = max_reduce_blocks_vol(G->g.nx, G->g.ny, G->g.nz);
@@ -337,8 +348,10 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
     auto fam = [&](int f) { return doffs + (size_t)f * (n + 1); };
     TVR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
-    if (total[F_BP] > 0)
-        le = launch_backproject_grouped<T>(dprobs, fam(F_BP), n, total[F_BP], cs);
+    for (int f = F_BP4; f <= F_BP8; ++f)
+        if (le == hipSuccess && total[f] > 0)
+            le = launch_backproject_grouped<T>(dprobs, fam(f), n, total[f],
+                                               BP_FAMILY_CZ[f - F_BP4], cs);
     if (le == hipSuccess && total[F_SP] > 0)
         le = launch_spmv_grouped<T>(dprobs, fam(F_SP), n, total[F_SP], cs);
     if (le == hipSuccess)
@@ -347,8 +360,10 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         le = launch_trial_grouped<T>(dprobs, fam(F_VOX), n, total[F_VOX], cs);
     if (le == hipSuccess)
         le = launch_transpose_grouped<T>(dprobs, fam(F_TR), n, total[F_TR], cs);
-    if (le == hipSuccess)
-        le = launch_project_grouped<T>(dprobs, fam(F_PJ), n, total[F_PJ], cs);
+    for (int f = F_PJ1; f <= F_PJ8; ++f)
+        if (le == hipSuccess && total[f] > 0)
+            le = launch_project_grouped<T>(dprobs, fam(f), n, total[f], PJ_FAMILY_TY[f - F_PJ1],
+                                           cs);
     if (le == hipSuccess)
         le = launch_finalize_grouped<T>(dprobs, n, cs);
     if (le == hipSuccess)

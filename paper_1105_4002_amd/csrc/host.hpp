@@ -22,6 +22,7 @@ struct tvreg_geometry {
     void *dev_tables;
     int64_t N, m;
     int pstride;  // partial-sum capacity per slot
+    int sym_off;  // 1: a stored transpose ignores the scan's symmetry (tvreg_set_symmetry)
 };
 
 namespace tvr {

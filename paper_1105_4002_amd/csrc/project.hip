@@ -117,17 +117,11 @@ __global__ __launch_bounds__(64 * TY) void project_kernel(GeomDev g, const T *__
 }
 
 // Batched: the trial points XB of every running problem (residual against
-// b, Bregman data term against RY).
-template <typename T>
-__global__ __launch_bounds__(64 * PJ_TY_DEFAULT) void project_grouped(BatchProblem<T> *probs,
-                                                               const int *offs, int n)
+// b, Bregman data term against RY), each problem with its own ray tile
+// (columns WC) among the problems whose tile has TY waves (one launch per TY).
+template <typename T, int WC, int TY>
+__device__ __forceinline__ void project_grouped_body(const BatchProblem<T> &P, int local)
 {
-    const int p = find_problem(offs, n, blockIdx.x);
-    const BatchProblem<T> &P = probs[p];
-    if (P.state != B_RUNNING)
-        return;
-    const int local = blockIdx.x - offs[p];
-    constexpr int WC = PJ_WC_DEFAULT, TY = PJ_TY_DEFAULT;
     int bx, by, v;
     decode_block(local, (P.g.cols + WC - 1) / WC, P.g.nviews, bx, by, v);
     if (P.g.cone)
@@ -138,21 +132,62 @@ __global__ __launch_bounds__(64 * PJ_TY_DEFAULT) void project_grouped(BatchProbl
                                                P.pstride, bx, by, v, local);
 }
 
+template <typename T, int TY>
+__global__ __launch_bounds__(64 * TY) void project_grouped(BatchProblem<T> *probs,
+                                                          const int *offs, int n)
+{
+    const int p = find_problem(offs, n, blockIdx.x);
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING)
+        return;
+    const int local = blockIdx.x - offs[p];
+    switch (P.g.pj_wc) {  // block-uniform
+    case 8:
+        project_grouped_body<T, 8, TY>(P, local);
+        break;
+    case 16:
+        project_grouped_body<T, 16, TY>(P, local);
+        break;
+    case 32:
+        project_grouped_body<T, 32, TY>(P, local);
+        break;
+    default:
+        project_grouped_body<T, 64, TY>(P, local);
+        break;
+    }
+}
+
 }  // namespace
 
 template <typename T>
 hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
-                                  hipStream_t st)
+                                  int waves, hipStream_t st)
 {
-    hipLaunchKernelGGL((project_grouped<T>), dim3(blocks), dim3(64, PJ_TY_DEFAULT), 0, st, probs,
-                       offs, n);
+    switch (waves) {
+    case 1:
+        hipLaunchKernelGGL((project_grouped<T, 1>), dim3(blocks), dim3(64, 1), 0, st, probs, offs,
+                           n);
+        break;
+    case 2:
+        hipLaunchKernelGGL((project_grouped<T, 2>), dim3(blocks), dim3(64, 2), 0, st, probs, offs,
+                           n);
+        break;
+    case 8:
+        hipLaunchKernelGGL((project_grouped<T, 8>), dim3(blocks), dim3(64, 8), 0, st, probs, offs,
+                           n);
+        break;
+    default:
+        hipLaunchKernelGGL((project_grouped<T, 4>), dim3(blocks), dim3(64, 4), 0, st, probs, offs,
+                           n);
+        break;
+    }
     return hipGetLastError();
 }
 
 template hipError_t launch_project_grouped<float>(BatchProblem<float> *, const int *, int, int,
-                                                  hipStream_t);
+                                                  int, hipStream_t);
 template hipError_t launch_project_grouped<double>(BatchProblem<double> *, const int *, int, int,
-                                                   hipStream_t);
+                                                   int, hipStream_t);
 
 namespace {
 

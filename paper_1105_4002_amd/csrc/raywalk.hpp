@@ -21,21 +21,22 @@ __device__ __forceinline__ void slab(double lo, double hi, double S, double invD
     }
 }
 
-// Visits the ray's voxels in order, calling visit(index, dt) with dt >= 0 the
-// parameter length inside the voxel (multiply by |D| for the length; dt may be
-// 0 where two crossings coincide).  Walks voxel to voxel: the next
-// crossing of each axis is plane_t(X) of the next plane X, the segment ends
-// at the nearest one, and every axis whose crossing is reached advances (a
-// tie of two axes is one crossing, so no zero-length piece is visited).
-// The exit crossing of each axis is computed with the same formula as the
-// slab exit, so no index leaves the volume before t reaches tmax.
-// The volume is read through strides (sx, sy) so that a y-fastest copy can
-// serve views whose rays run mostly along x (adjacent detector columns then
-// touch adjacent addresses).  CLAMP clamps each visited index to the volume
-// as well (for loads without a hardware range check).
-template <bool CONE, bool CLAMP, class Visit>
-__device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry &ce,
-                                               const RowEntry &re, int sx, int sy, Visit &&visit)
+// The walk itself.  Calls enter(ix, iy, iz, px, py, pz) once with the entry
+// voxel and the direction of travel along each axis (true: increasing
+// index), then, voxel by voxel, visit(dt) with dt >= 0 the parameter length
+// inside the current voxel (multiply by |D| for the length; dt may be 0 where
+// two crossings coincide) followed, unless the ray has left the volume, by
+// move(ax, ay, az): which axes' planes the ray crosses into the next voxel.
+// The next crossing of each axis is plane_t(X) of the next plane X, the
+// segment ends at the nearest one, and every axis whose crossing is reached
+// advances (a tie of two axes is one crossing, so no zero-length piece is
+// visited).  The exit crossing of each axis is computed with the same formula
+// as the slab exit, so no voxel outside the volume is reached before t
+// reaches tmax.
+template <bool CONE, class Enter, class Visit, class Move>
+__device__ __forceinline__ void ray_walk_core(const GeomDev &g, const ColEntry &ce,
+                                              const RowEntry &re, Enter &&enter, Visit &&visit,
+                                              Move &&move)
 {
     const double lox = -g.hx, loy = -g.hy, loz = -g.hz;
     double tmin = CONE ? 0.0 : -INFINITY;
@@ -57,6 +58,7 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
     iz = min(max(iz, 0), g.nz - 1);
 
     const bool px = ce.Dx > 0.0, py = ce.Dy > 0.0, pz = re.Dz > 0.0;
+    enter(ix, iy, iz, px, py, pz);
     // An axis the ray runs parallel to gets the crossing offset +inf:
     // fma(X, 0, +inf) = +inf, so its crossing is never reached.
     const double ox = ce.invDx != 0.0 ? ce.ox : INFINITY;
@@ -72,12 +74,6 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
     double tnx = plane_t(Xn, ce.invDx, ox);
     double tny = plane_t(Yn, ce.invDy, oy);
     double tnz = plane_t(Zn, re.invDz, oz);
-    const int sz = g.nx * g.ny;
-    const int stx = px ? sx : -sx;
-    const int sty = py ? sy : -sy;
-    const int stz = pz ? sz : -sz;
-    const unsigned last = (unsigned)(g.nx * g.ny * g.nz - 1);
-    int idx = ix * sx + iy * sy + iz * sz;
 
     // Every crossing after the first is >= the one before it (fma rounds
     // monotonically and invD has the sign of the plane step), so segment
@@ -87,12 +83,12 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
     const int cap = g.nx + g.ny + g.nz + 2;  // hard bound on the number of voxels
     for (int it = 0; it < cap; ++it) {
         const double tn = fmin(fmin(tnx, tny), fmin(tnz, tmax));
-        visit(CLAMP ? min((unsigned)idx, last) : (unsigned)idx, tn - t);
+        visit(tn - t);
         t = tn;
         if (!(t < tmax))
             break;
         const bool ax = tnx <= tn, ay = tny <= tn, az = tnz <= tn;
-        idx += (ax ? stx : 0) + (ay ? sty : 0) + (az ? stz : 0);
+        move(ax, ay, az);
         // every reached axis moves to its next plane and the others add 0;
         // all three crossings are then recomputed, an unmoved plane giving
         // its previous crossing again bit for bit
@@ -103,6 +99,33 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
         tny = plane_t(Yn, ce.invDy, oy);
         tnz = plane_t(Zn, re.invDz, oz);
     }
+}
+
+// Visits the ray's voxels in order, calling visit(index, dt) (the walk of
+// ray_walk_core with the voxel's index into the volume).  The volume is read
+// through strides (sx, sy) so that a y-fastest copy can serve views whose
+// rays run mostly along x (adjacent detector columns then touch adjacent
+// addresses).  CLAMP clamps each visited index to the volume as well (for
+// loads without a hardware range check).
+template <bool CONE, bool CLAMP, class Visit>
+__device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry &ce,
+                                               const RowEntry &re, int sx, int sy, Visit &&visit)
+{
+    const int sz = g.nx * g.ny;
+    const unsigned last = (unsigned)(g.nx * g.ny * g.nz - 1);
+    int idx = 0, stx = 0, sty = 0, stz = 0;
+    ray_walk_core<CONE>(
+        g, ce, re,
+        [&](int ix, int iy, int iz, bool px, bool py, bool pz) {
+            stx = px ? sx : -sx;
+            sty = py ? sy : -sy;
+            stz = pz ? sz : -sz;
+            idx = ix * sx + iy * sy + iz * sz;
+        },
+        [&](double dt) { visit(CLAMP ? min((unsigned)idx, last) : (unsigned)idx, dt); },
+        [&](bool ax, bool ay, bool az) {
+            idx += (ax ? stx : 0) + (ay ? sty : 0) + (az ? stz : 0);
+        });
 }
 
 // Loads of x[idx] through a buffer resource: the hardware checks each offset

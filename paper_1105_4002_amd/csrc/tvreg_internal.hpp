@@ -67,14 +67,30 @@ __host__ __device__ __forceinline__ bool mat_voxel(int nx, int ny, int64_t s, in
     return x < nx && y < ny;
 }
 
+// Symmetry of a circular scan.  With views evenly spaced over the full
+// circle (V divisible by 4), a square even volume and an even detector, the
+// turn of the volume by a quarter about z carries ray (v, row, col) onto ray
+// (v + V/4, row, col) and voxel (i, j, k) onto (nx - 1 - j, i, k) with the
+// same length; with V even and an even volume, the half turn carries view v
+// onto v + V/2 and (i, j) onto (nx - 1 - i, ny - 1 - j); with an even nz and
+// an even detector, the mirror z -> -z carries row r onto rows - 1 - r and
+// k onto nz - 1 - k.  The stored transpose then holds only the voxels of one
+// cell i < mx, j < my, k < mz of the group (a quadrant or half of the plane,
+// the lower half in z) and each entry serves rot * (mir ? 2 : 1) voxels.
+// Entries of such a layout carry a packed ray key (view << (kc + kr)) |
+// (row << kc) | col instead of the ray index.
 struct MatDev {
     int present;                     // 0: A^T evaluated on the fly
     int64_t sv;                      // slices of voxels
     const int64_t *off_v;            // first entry of each slice
     const int32_t *w_v;              // slice widths (max entries of a lane)
-    const int32_t *cnt_v;            // entries of each voxel
+    const int32_t *cnt_v;            // entries of each stored voxel (mx x my x mz)
     const void *val_v;               // a_ij
-    const int32_t *idx_v;            // ray index of each entry
+    const int32_t *idx_v;            // ray index (rot = 1, mir = 0) or packed ray key
+    int rot;                         // 1, 2 (half turns) or 4 (quarter turns)
+    int mir;                         // 1: the z mirror is used
+    int mx, my, mz;                  // stored cell (the whole volume when rot = 1, mir = 0)
+    int kc, kr;                      // bits of the column and row fields of a key
 };
 
 struct GeomDev {
@@ -96,6 +112,8 @@ struct GeomDev {
     int pj_ty;                 // projector: ray tiles (waves) per block, stacked along rows (1, 2, 4, 8)
     int bp_cz;                 // on-the-fly backprojector: voxels per thread along z (4, 8, 16)
     int flat_row;              // cone: the detector row with w = 0 (invDz = 0), else -1
+    int sym_rot;               // the scan's symmetry group a stored A^T may use (see MatDev):
+    int sym_mir;               // turns (1, 2 or 4) and the z mirror (0 or 1)
 };
 
 // default tile shapes (the batched solve always uses these)
@@ -242,6 +260,7 @@ int project_blocks_max(const GeomDev &g);
 int max_reduce_blocks_vol(int nx, int ny, int nz);
 int elementwise_blocks(int64_t n);
 int backproject_blocks(const GeomDev &g);
+int backproject_depth(const GeomDev &g);  // the geometry's voxel depth: 4, 8 or 16
 int transpose_blocks(int nx, int ny, int nz);
 
 // ------------------------------------------------------------ batched solve
@@ -271,10 +290,11 @@ struct BatchProblem {
     int iters, grad_evals, func_evals;
 };
 
-// Grouped launches; offs[p] = first block of problem p (n + 1 entries).
+// Grouped launches; offs[p] = first block of problem p (n + 1 entries).  The
+// on-the-fly backprojector takes the problems of one voxel depth (4 or 8).
 template <typename T>
 hipError_t launch_backproject_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
-                                      hipStream_t st);
+                                      int depth, hipStream_t st);
 // the problems with a stored transpose (the on-the-fly kernel above takes the others)
 template <typename T>
 hipError_t launch_spmv_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
@@ -291,7 +311,7 @@ hipError_t launch_transpose_grouped(BatchProblem<T> *probs, const int *offs, int
                                     hipStream_t st);
 template <typename T>
 hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
-                                  hipStream_t st);
+                                  int waves, hipStream_t st);
 template <typename T>
 hipError_t launch_extrapolate_grouped(BatchProblem<T> *probs, const int *offs, int n,
                                       int blocks, hipStream_t st);

@@ -29,17 +29,38 @@ def test_kernel_models_are_positive_and_bounded():
         for stored in (False, True):
             bound, amount, unit, peak = b.kernel_model(name, N, m, nnz, 4, stored)
             assert bound in ("hbm", "alu") and amount > 0 and peak > 0
-            assert unit in ("GB/s", "TFLOP/s")
-    # the stored product moves 8 bytes per non-zero plus r and the volume
+            assert unit in ("GB/s", "TFLOP/s", "T lane-instr/s")
+    # the stored product, in the gather model: one value of r per non-zero,
+    # the volume written and its compulsory second pass (8 B per voxel)
     _, amount, _, _ = b.kernel_model("backproject", N, m, nnz, 4, True)
-    assert amount == 8 * nnz + 4 * (m + N)
+    assert amount == 4 * nnz + 8 * N
+    # the projector against the issue rate: its vector instructions per step
+    bound, amount, unit, peak = b.kernel_model("project", N, m, nnz, 4, True)
+    assert bound == "alu" and amount == b.PROJECT_VALU_PER_STEP * nnz
+    assert peak == 256 * 64 * 2.4e9
 
 
 def test_measured_traffic_is_tied_to_the_kernel_text():
+    """Each measured figure is reported only for the form it was measured on
+    (projector at its ray tile, the stored product only with a stored A^T)
+    and only while its sources hash to the measured text."""
     b = load_bench()
-    src = b.kernel_source(os.path.join(ROOT, b.MEASURED_TRAFFIC["source"]),
-                          b.MEASURED_TRAFFIC["function"])
-    assert src.startswith("constexpr int MB")
-    assert "void spmv_voxels_block(" in src and src.rstrip().endswith("}")
-    assert b.measured_traffic("project", True) is None
+    for name, e in b.MEASURED_TRAFFIC.items():
+        assert e["bytes"] > 0 and len(e["sha256_prefix"]) == 16
+        for p in e["sources"]:
+            assert os.path.isfile(os.path.join(ROOT, p))
+    assert b.measured_traffic("tv", True) is None
     assert b.measured_traffic("backproject", False) is None
+    assert b.measured_traffic("project", True, (8, 8)) is None
+    e = b.MEASURED_TRAFFIC["project"]
+    current = b.sources_sha(e["sources"]).startswith(e["sha256_prefix"])
+    got = b.measured_traffic("project", True, e["tile"])
+    assert (got is not None) == current
+    if got is not None:
+        assert got == round(e["bytes"] / 1e9, 3)
+    saved = e["sha256_prefix"]
+    try:
+        e["sha256_prefix"] = "0" * 16
+        assert b.measured_traffic("project", True, e["tile"]) is None
+    finally:
+        e["sha256_prefix"] = saved

@@ -125,6 +125,36 @@ def test_batched_equals_single_solves(prec, poll):
     assert torch.equal(singles[4][0], x0s[4].clamp_min(0))
 
 
+# (projector tile columns, waves per block, backprojector depth), one per
+# problem of mixed_problems(): every block shape and tile width appears
+TUNED_SHAPES = [(16, 2, 4), (8, 8, 16), (32, 1, 8), (64, 8, 4), (8, 1, 16), (64, 2, 4)]
+
+
+@pytest.mark.parametrize("prec", [tv.F64, tv.F32])
+def test_batched_equals_single_solves_under_tuned_shapes(prec):
+    """Each problem of a batch runs its own geometry's tile shapes (the
+    grouped projector is launched once per block shape, each problem with
+    its own tile width; the grouped backprojector takes each problem's
+    depth), so the batch still equals the single solves bit for bit."""
+    print(f"batch vs single, tuned shapes, prec={prec}", flush=True)
+    probs = mixed_problems()
+    geoms, bs, x0s, kws = [], [], [], []
+    for (geom, seed, kw, start), shape in zip(probs, TUNED_SHAPES):
+        G = tv.Geometry(geom, prec)
+        G.set_tuning(*shape)
+        assert G.tuning == shape
+        geoms.append(G)
+        b, x0 = make_inputs(geom, seed, start, prec)
+        bs.append(b)
+        x0s.append(x0)
+        kws.append(single_kwargs(kw))
+    singles = [tv.solve(G, b, tau=1e-4, x0=x0, **kw)[:2]
+               for G, b, x0, kw in zip(geoms, bs, x0s, kws)]
+    xb, ib, _ = batched(geoms, bs, x0s, kws, 8)
+    for i in range(len(probs)):
+        assert_same(xb[i], ib[i], singles[i][0], singles[i][1], f"problem {i}")
+
+
 def test_batched_start_point_untouched_and_inputs_reusable():
     probs = mixed_problems()[:2]
     geoms, bs, x0s, kws, singles = run_both(probs, tv.F32)
