@@ -88,11 +88,13 @@ FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed 
 # vector instruction issue: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s
 # vector instructions per voxel step of the projector's walk loop (count of the
-# gfx950 code the build emits for project_kernel on volumes under 2 GiB: 3 min,
-# 1 compare and the loop exit; 3 compares, 3 selects and 2 adds for the index;
-# 3 high-word selects, 3 adds and 3 FMAs for the planes and next crossings;
-# length, move, 32-bit load offset, convert and accumulate)
-PROJECT_VALU_PER_STEP = 28
+# gfx950 code the build emits for project_kernel on volumes under 2 GiB, the
+# same for the 2 x 32 and 64 x 1 ray tiles: 3 min and 1 compare for the
+# segment end; decrement and compare of the iteration bound; 3 compares, 3
+# selects and 2 adds for the index; 3 high-word selects, 1 move of the zero
+# low word, 3 adds and 3 FMAs for the planes and next crossings; length,
+# move, 32-bit load offset, convert and accumulate)
+PROJECT_VALU_PER_STEP = 29
 
 
 def log(msg: str) -> None:
@@ -622,9 +624,12 @@ def main() -> int:
                   "backproject_depth": t["backproject_depth"],
                   "project_ms": round(t["project_ms"][(t["project_tile_cols"],
                                                        t["project_waves"])], 4),
-                  "project_ms_default_shape": round(t["project_ms"][(64, 4)], 4),
-                  "project_ms_8x8_tiles": round(min(v for (c, _), v in t["project_ms"].items()
-                                                    if c == 8), 4),
+                  # the best row tile (64 x 1 .. 8 x 8 rays per wave) and the
+                  # best column tile (1 x 64, 2 x 32), each at its best height
+                  "project_ms_row_tiles": round(min(v for (c, _), v in t["project_ms"].items()
+                                                    if c >= 8), 4),
+                  "project_ms_column_tiles": round(min(v for (c, _), v in
+                                                       t["project_ms"].items() if c <= 2), 4),
                   "backproject_on_the_fly_ms": round(t["backproject_ms"][t["backproject_depth"]],
                                                      4)}
         log(f"  {tuning}")

@@ -177,7 +177,13 @@ tvreg_status tvreg_matrix_detach(tvreg_geometry *geom);
  * of the solver's FP64 sums, follow the shape).
  *   project_tile_cols  detector columns of the ray tile one wavefront walks;
  *                      the tile is project_tile_cols x (64 / project_tile_cols)
- *                      pixels: 8, 16, 32 or 64 (default);
+ *                      pixels: 1, 2 (column tiles), 8, 16, 32 or 64 (row
+ *                      tiles); default 2 for a detector with a multiple of
+ *                      32 rows, else 64.  Inside
+ *                      the solvers the projector reads a companion copy of
+ *                      the volume made before each projection (z fastest for
+ *                      column tiles, y fastest for row tiles);
+ *                      tvreg_project reads the volume itself;
  *   project_waves      ray tiles per projector block, stacked along the
  *                      detector rows: 1, 2, 4 (default) or 8;
  *   backproject_depth  voxels per thread along z in the on-the-fly
@@ -196,8 +202,8 @@ typedef struct {
     int32_t project_waves;
     int32_t backproject_depth;
     int32_t reserved;            /* 0 */
-    double project_ms[4][4];     /* tvreg_autotune: ms per projection, [tile cols 8, 16, 32, 64]
-                                    [waves 1, 2, 4, 8] */
+    double project_ms[6][4];     /* tvreg_autotune: ms per projection, [tile cols 1, 2, 8, 16,
+                                    32, 64][waves 1, 2, 4, 8] */
     double backproject_ms[3];    /* tvreg_autotune: ms per backprojection for depth 4, 8, 16 */
 } tvreg_tuning;
 size_t tvreg_autotune_workspace_bytes(const tvreg_geometry *geom);

@@ -52,11 +52,11 @@ class _SolveParams(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("project_tile_cols", ctypes.c_int32), ("project_waves", ctypes.c_int32),
                 ("backproject_depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("project_ms", (ctypes.c_double * 4) * 4),
+                ("project_ms", (ctypes.c_double * 4) * 6),
                 ("backproject_ms", ctypes.c_double * 3)]
 
 
-PROJECT_TILE_COLS = (8, 16, 32, 64)
+PROJECT_TILE_COLS = (1, 2, 8, 16, 32, 64)
 PROJECT_WAVES = (1, 2, 4, 8)
 BACKPROJECT_DEPTHS = (4, 8, 16)
 

@@ -306,7 +306,7 @@ extern "C" tvreg_status tvreg_create_geometry(const tvreg_geometry_desc *d,
     g.beam3d = p3 ? 1 : 0;
     g.v3 = p3 ? (const View3 *)(base + o_v3) : nullptr;
     g.mat = MatDev{};
-    g.pj_wc = PJ_WC_DEFAULT;
+    g.pj_wc = default_tile_cols(Rw);
     g.pj_ty = PJ_TY_DEFAULT;
     g.bp_cz = BP_CZ_DEFAULT;
     g.flat_row = -1;
@@ -694,13 +694,13 @@ struct Solver {
     int64_t N, m;
     T *vN[5];
     T *vM[3];
-    T *xt;  // y-fastest copy of the volume being projected
+    T *xt;  // the projector's companion copy of the volume being projected
 
     tvreg_status project(const T *x, T *out, const T *rref)
     {
         int nb = 0;
         TVR_HIP(run.timed(TVREG_KERNEL_TRANSPOSE,
-                          [&] { return launch_transpose_xy<T>(nx, ny, nz, x, xt, run.st); }));
+                          [&] { return launch_companion<T>(G->g, x, xt, run.st); }));
         TVR_HIP(run.timed(TVREG_KERNEL_PROJECT, [&] {
             return launch_project<T>(G->g, x, xt, b, out, rref, run.part, run.pstride, run.st,
                                      &nb);
@@ -999,7 +999,7 @@ static tvreg_status objective_impl(const tvreg_geometry *G, const T *b, double a
     double *part = (double *)((char *)xt + align_up(sizeof(T) * (size_t)G->N, 256));
     double *sc = (double *)((char *)part + partial_bytes(G->pstride));
     int nb1 = 0, nb2 = 0;
-    TVR_HIP(launch_transpose_xy<T>(G->g.nx, G->g.ny, G->g.nz, x, xt, st));
+    TVR_HIP(launch_companion<T>(G->g, x, xt, st));
     TVR_HIP(launch_project<T>(G->g, x, xt, b, r, nullptr, part, G->pstride, st, &nb1));
     TVR_HIP(launch_backproject<T>(G->g, r, grad, st));
     TVR_HIP(launch_tv<T>(G->g.nx, G->g.ny, G->g.nz, tau, alpha, x, nullptr, grad, grad, part,

@@ -155,13 +155,15 @@ template hipError_t launch_control_batched<double>(BatchProblem<double> *, int, 
 namespace {
 
 // Kernel families of a round, each with its own prefix table of block counts.
-// The on-the-fly backprojector has one family per voxel depth (F_BP4 ..
-// F_BP8) and the projector one per block shape (waves per block, 1, 2, 4 or
-// 8: F_PJ1 .. F_PJ8), so that every problem runs its own tuned tiles, each
-// family in a kernel compiled for that shape alone.
-enum Family : int { F_BP4 = 0, F_BP8, F_SP, F_VOX, F_TR, F_PJ1, F_PJ2, F_PJ4, F_PJ8, F_EX, F_COUNT };
-constexpr int BP_FAMILY_CZ[2] = {4, 8};
+// The on-the-fly backprojector has one family per voxel depth (F_BP4,
+// F_BP8) and the projector one per ray tile (6 widths x 4 block heights,
+// from F_PJ), so that every problem runs its own tuned tiles, each family in
+// a kernel compiled for that shape alone.
+constexpr int PJ_FAMILY_WC[6] = {1, 2, 8, 16, 32, 64};
 constexpr int PJ_FAMILY_TY[4] = {1, 2, 4, 8};
+constexpr int N_PJ = 24;
+enum Family : int { F_BP4 = 0, F_BP8, F_SP, F_VOX, F_TR, F_EX, F_PJ, F_COUNT = F_PJ + N_PJ };
+constexpr int BP_FAMILY_CZ[2] = {4, 8};
 
 // Per-problem region: X, XB, YB, G, XT (N values each), RX, RXB, RYB (m
 // each), the partial-sum slots and the finalised sums.
@@ -202,8 +204,18 @@ size_t batch_bytes(int n, const tvreg_geometry *const *geoms, std::vector<size_t
     return off;
 }
 
-// waves per projector block of a geometry's ray tile (the tuner's values)
-int pj_waves(const GeomDev &g) { return g.pj_ty == 1 || g.pj_ty == 2 || g.pj_ty == 8 ? g.pj_ty : 4; }
+// the projector family of a geometry's ray tile (the tuner's values)
+int pj_family(const GeomDev &g)
+{
+    int a = 5, i = 2;  // 64 columns, 4 waves
+    for (int k = 0; k < 6; ++k)
+        if (PJ_FAMILY_WC[k] == g.pj_wc)
+            a = k;
+    for (int k = 0; k < 4; ++k)
+        if (PJ_FAMILY_TY[k] == g.pj_ty)
+            i = k;
+    return F_PJ + 4 * a + i;
+}
 
 // Grouped launches run every problem with its geometry's tile shapes (and its
 // stored transpose, when attached), except a backprojector depth of 16, which
@@ -219,8 +231,8 @@ GeomDev batch_shapes(const GeomDev &g0)
 int family_blocks(const tvreg_geometry *G, int f)
 {
     const GeomDev g = batch_shapes(G->g);
-    if (f >= F_PJ1 && f <= F_PJ8)
-        return pj_waves(g) == PJ_FAMILY_TY[f - F_PJ1] ? project_blocks(g) : 0;
+    if (f >= F_PJ)
+        return pj_family(g) == f ? project_blocks(g) : 0;
     if (f >= F_BP4 && f <= F_BP8)
         return !g.mat.present && backproject_depth(g) == BP_FAMILY_CZ[f - F_BP4]
                    ? backproject_blocks(g)
@@ -231,7 +243,7 @@ int family_blocks(const tvreg_geometry *G, int f)
     case F_VOX:
         return max_reduce_blocks_vol(g.nx, g.ny, g.nz);
     case F_TR:
-        return transpose_blocks(g.nx, g.ny, g.nz);
+        return companion_blocks(g);
     default:
         return elementwise_blocks(G->N) + elementwise_blocks(G->m);
     }
@@ -316,7 +328,7 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         P.grad_evals = 1;
         const GeomDev &g = P.g;
         TVR_HIP(launch_clip<T>(G->N, (const T *)x_io[i], P.X, P.box, st));
-        TVR_HIP(launch_transpose_xy<T>(g.nx, g.ny, g.nz, P.X, P.XT, st));
+        TVR_HIP(launch_companion<T>(g, P.X, P.XT, st));
         TVR_HIP(launch_project<T>(g, P.X, P.XT, P.b, P.RX, nullptr, P.part, P.pstride, st,
                                   nullptr));
         TVR_HIP(launch_backproject<T>(g, P.RX, P.G, st));
@@ -360,10 +372,11 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         le = launch_trial_grouped<T>(dprobs, fam(F_VOX), n, total[F_VOX], cs);
     if (le == hipSuccess)
         le = launch_transpose_grouped<T>(dprobs, fam(F_TR), n, total[F_TR], cs);
-    for (int f = F_PJ1; f <= F_PJ8; ++f)
+    for (int f = F_PJ; f < F_COUNT; ++f)
         if (le == hipSuccess && total[f] > 0)
-            le = launch_project_grouped<T>(dprobs, fam(f), n, total[f], PJ_FAMILY_TY[f - F_PJ1],
-                                           cs);
+            le = launch_project_grouped<T>(dprobs, fam(f), n, total[f],
+                                           PJ_FAMILY_WC[(f - F_PJ) / 4],
+                                           PJ_FAMILY_TY[(f - F_PJ) % 4], cs);
     if (le == hipSuccess)
         le = launch_finalize_grouped<T>(dprobs, n, cs);
     if (le == hipSuccess)

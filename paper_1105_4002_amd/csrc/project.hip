@@ -24,10 +24,18 @@ namespace {
 
 // Ray tiles.  A wavefront of 64 threads walks the rays of a WC x (64 / WC)
 // patch of detector pixels (columns x rows); a block stacks TY such patches
-// along the rows.  Neighbouring rays have similar lengths through the
-// volume, so a square patch keeps more lanes busy until the wave's longest
-// ray ends than a 64 x 1 strip does (in a cone beam, the strip mixes rays
-// through the middle of the volume with rays that only clip an edge).
+// along the rows.  A wave runs until its longest ray ends, and its lanes
+// read the volume together, so a tile trades balance against locality.
+// Along a detector row the ray lengths vary widely (a 64 x 1 strip mixes
+// rays through the middle of the volume with rays that only clip an edge:
+// 77 % of the lane steps are useful at 256^3), while down a detector column
+// they barely change (96 %): the rays of one column share their path across
+// the xy plane and differ only in slope along z.  Column tiles (WC = 1, 2)
+// therefore keep nearly every lane busy, and read the z-fastest companion
+// copy [y][x][z], in which the lanes of a wave, at neighbouring heights of
+// the same xy cells, touch adjacent addresses.  Row tiles (WC >= 8) read x
+// itself, or its y-fastest companion [z][x][y] for views whose rays run
+// mostly along x.
 template <int WC>
 struct RayTile {
     static constexpr int rows = 64 / WC;  // detector rows per wave
@@ -78,11 +86,20 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
             ce = g.col[(size_t)v * g.cols + col];
             re = g.row[row];
         }
-        // rays mostly along x read the y-fastest copy when one is given
-        const double cv = g.cs[v].x, sv = g.cs[v].y;
-        const bool use_t = xt != nullptr && fabs(cv) > fabs(sv);
-        const double s = ray_walk<T, CONE, BUF>(g, use_t ? xt : x, ce, re, use_t ? g.ny : 1,
-                                                use_t ? 1 : g.nx);
+        // the companion copy when one is given (block-uniform choice)
+        const T *xs = x;
+        int sx = 1, sy = g.nx, sz = g.nx * g.ny;
+        if (xt != nullptr && column_tiles(WC)) {
+            xs = xt;
+            sx = g.nz;
+            sy = g.nx * g.nz;
+            sz = 1;
+        } else if (xt != nullptr && fabs(g.cs[v].x) > fabs(g.cs[v].y)) {
+            xs = xt;
+            sx = g.ny;
+            sy = 1;
+        }
+        const double s = ray_walk<T, CONE, BUF>(g, xs, ce, re, sx, sy, sz);
         const double dn = CONE ? g.dnorm[(size_t)row * g.cols + col] : g.dnorm[v];
         const size_t i = ((size_t)v * g.rows + row) * g.cols + col;
         double ri = s * dn;
@@ -117,22 +134,9 @@ __global__ __launch_bounds__(64 * TY) void project_kernel(GeomDev g, const T *__
 }
 
 // Batched: the trial points XB of every running problem (residual against
-// b, Bregman data term against RY), each problem with its own ray tile
-// (columns WC) among the problems whose tile has TY waves (one launch per TY).
+// b, Bregman data term against RY), one launch per ray tile shape (WC
+// columns, TY waves) over the problems of that shape.
 template <typename T, int WC, int TY>
-__device__ __forceinline__ void project_grouped_body(const BatchProblem<T> &P, int local)
-{
-    int bx, by, v;
-    decode_block(local, (P.g.cols + WC - 1) / WC, P.g.nviews, bx, by, v);
-    if (P.g.cone)
-        project_block<T, true, WC, TY, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
-                                              P.pstride, bx, by, v, local);
-    else
-        project_block<T, false, WC, TY, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
-                                               P.pstride, bx, by, v, local);
-}
-
-template <typename T, int TY>
 __global__ __launch_bounds__(64 * TY) void project_grouped(BatchProblem<T> *probs,
                                                           const int *offs, int n)
 {
@@ -141,53 +145,67 @@ __global__ __launch_bounds__(64 * TY) void project_grouped(BatchProblem<T> *prob
     if (P.state != B_RUNNING)
         return;
     const int local = blockIdx.x - offs[p];
-    switch (P.g.pj_wc) {  // block-uniform
+    int bx, by, v;
+    decode_block(local, (P.g.cols + WC - 1) / WC, P.g.nviews, bx, by, v);
+    if (P.g.cone)  // block-uniform
+        project_block<T, true, WC, TY, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
+                                              P.pstride, bx, by, v, local);
+    else
+        project_block<T, false, WC, TY, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
+                                               P.pstride, bx, by, v, local);
+}
+
+template <typename T, int WC>
+hipError_t launch_grouped_wc(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                             int waves, hipStream_t st)
+{
+    switch (waves) {
+    case 1:
+        hipLaunchKernelGGL((project_grouped<T, WC, 1>), dim3(blocks), dim3(64, 1), 0, st, probs,
+                           offs, n);
+        break;
+    case 2:
+        hipLaunchKernelGGL((project_grouped<T, WC, 2>), dim3(blocks), dim3(64, 2), 0, st, probs,
+                           offs, n);
+        break;
     case 8:
-        project_grouped_body<T, 8, TY>(P, local);
-        break;
-    case 16:
-        project_grouped_body<T, 16, TY>(P, local);
-        break;
-    case 32:
-        project_grouped_body<T, 32, TY>(P, local);
+        hipLaunchKernelGGL((project_grouped<T, WC, 8>), dim3(blocks), dim3(64, 8), 0, st, probs,
+                           offs, n);
         break;
     default:
-        project_grouped_body<T, 64, TY>(P, local);
+        hipLaunchKernelGGL((project_grouped<T, WC, 4>), dim3(blocks), dim3(64, 4), 0, st, probs,
+                           offs, n);
         break;
     }
+    return hipGetLastError();
 }
 
 }  // namespace
 
 template <typename T>
 hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
-                                  int waves, hipStream_t st)
+                                  int cols, int waves, hipStream_t st)
 {
-    switch (waves) {
+    switch (cols) {
     case 1:
-        hipLaunchKernelGGL((project_grouped<T, 1>), dim3(blocks), dim3(64, 1), 0, st, probs, offs,
-                           n);
-        break;
+        return launch_grouped_wc<T, 1>(probs, offs, n, blocks, waves, st);
     case 2:
-        hipLaunchKernelGGL((project_grouped<T, 2>), dim3(blocks), dim3(64, 2), 0, st, probs, offs,
-                           n);
-        break;
+        return launch_grouped_wc<T, 2>(probs, offs, n, blocks, waves, st);
     case 8:
-        hipLaunchKernelGGL((project_grouped<T, 8>), dim3(blocks), dim3(64, 8), 0, st, probs, offs,
-                           n);
-        break;
+        return launch_grouped_wc<T, 8>(probs, offs, n, blocks, waves, st);
+    case 16:
+        return launch_grouped_wc<T, 16>(probs, offs, n, blocks, waves, st);
+    case 32:
+        return launch_grouped_wc<T, 32>(probs, offs, n, blocks, waves, st);
     default:
-        hipLaunchKernelGGL((project_grouped<T, 4>), dim3(blocks), dim3(64, 4), 0, st, probs, offs,
-                           n);
-        break;
+        return launch_grouped_wc<T, 64>(probs, offs, n, blocks, waves, st);
     }
-    return hipGetLastError();
 }
 
 template hipError_t launch_project_grouped<float>(BatchProblem<float> *, const int *, int, int,
-                                                  int, hipStream_t);
+                                                  int, int, hipStream_t);
 template hipError_t launch_project_grouped<double>(BatchProblem<double> *, const int *, int, int,
-                                                   int, hipStream_t);
+                                                   int, int, hipStream_t);
 
 namespace {
 
@@ -239,7 +257,7 @@ void launch_wc(const GeomDev &g, const T *x, const T *xt, const T *b, T *out, co
 }
 
 int valid_ty(int ty) { return ty == 1 || ty == 2 || ty == 8 ? ty : 4; }
-int valid_wc(int wc) { return wc == 8 || wc == 16 || wc == 32 ? wc : 64; }
+int valid_wc(int wc) { return wc == 1 || wc == 2 || wc == 8 || wc == 16 || wc == 32 ? wc : 64; }
 
 }  // namespace
 
@@ -251,6 +269,12 @@ hipError_t launch_project(const GeomDev &g, const T *x, const T *xt, const T *b,
     if (nblocks)
         *nblocks = project_blocks(g);
     switch (valid_wc(g.pj_wc)) {
+    case 1:
+        launch_wc<T, 1>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
+    case 2:
+        launch_wc<T, 2>(g, x, xt, b, out, rref, partials, pstride, st);
+        break;
     case 8:
         launch_wc<T, 8>(g, x, xt, b, out, rref, partials, pstride, st);
         break;
@@ -272,7 +296,7 @@ int project_blocks(const GeomDev &g) { return grid_blocks(g, valid_wc(g.pj_wc), 
 int project_blocks_max(const GeomDev &g)
 {
     int mx = 0;
-    for (int wc = 8; wc <= 64; wc *= 2)  // one wave per block gives the most blocks
+    for (int wc : {1, 2, 8, 16, 32, 64})  // one wave per block gives the most blocks
         mx = std::max(mx, grid_blocks(g, wc, 1));
     return mx;
 }

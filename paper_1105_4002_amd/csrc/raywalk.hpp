@@ -103,15 +103,15 @@ __device__ __forceinline__ void ray_walk_core(const GeomDev &g, const ColEntry &
 
 // Visits the ray's voxels in order, calling visit(index, dt) (the walk of
 // ray_walk_core with the voxel's index into the volume).  The volume is read
-// through strides (sx, sy) so that a y-fastest copy can serve views whose
-// rays run mostly along x (adjacent detector columns then touch adjacent
-// addresses).  CLAMP clamps each visited index to the volume as well (for
-// loads without a hardware range check).
+// through strides (sx, sy, sz), so that a copy stored in another axis order
+// can serve rays whose neighbours then touch adjacent addresses.  CLAMP
+// clamps each visited index to the volume as well (for loads without a
+// hardware range check).
 template <bool CONE, bool CLAMP, class Visit>
 __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry &ce,
-                                               const RowEntry &re, int sx, int sy, Visit &&visit)
+                                               const RowEntry &re, int sx, int sy, int sz,
+                                               Visit &&visit)
 {
-    const int sz = g.nx * g.ny;
     const unsigned last = (unsigned)(g.nx * g.ny * g.nz - 1);
     int idx = 0, stx = 0, sty = 0, stz = 0;
     ray_walk_core<CONE>(
@@ -156,18 +156,18 @@ __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uns
 template <typename T, bool CONE, bool BUF>
 __device__ __forceinline__ double ray_walk(const GeomDev &g, const T *__restrict__ x,
                                            const ColEntry &ce, const RowEntry &re, int sx,
-                                           int sy)
+                                           int sy, int sz)
 {
     double acc = 0.0;
     if (BUF) {
         const int bytes = (int)(sizeof(T) * (size_t)g.nx * g.ny * g.nz);
         const __amdgpu_buffer_rsrc_t xr =
             __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, bytes, BUF_WORD3);
-        ray_walk_visit<CONE, false>(g, ce, re, sx, sy, [&](unsigned idx, double dt) {
+        ray_walk_visit<CONE, false>(g, ce, re, sx, sy, sz, [&](unsigned idx, double dt) {
             acc = fma(dt, buf_load<T>(xr, idx), acc);
         });
     } else {
-        ray_walk_visit<CONE, true>(g, ce, re, sx, sy, [&](unsigned idx, double dt) {
+        ray_walk_visit<CONE, true>(g, ce, re, sx, sy, sz, [&](unsigned idx, double dt) {
             acc = fma(dt, (double)x[idx], acc);
         });
     }

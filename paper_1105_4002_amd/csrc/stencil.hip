@@ -393,8 +393,9 @@ __global__ __launch_bounds__(VX *VY) void trial_grouped(BatchProblem<T> *probs, 
                    P.part, P.pstride, bx, by, bz, local);
 }
 
-// xt[z][x][y] = x[z][y][x] through a 32 x 32 LDS tile per block (both the
-// read and the write are coalesced); the padding column avoids bank conflicts.
+// Slice z of a stack of ny x nx matrices, transposed: xt[z][x][y] =
+// x[z][y][x], through a 32 x 32 LDS tile per block (both the read and the
+// write are coalesced); the padding column avoids bank conflicts.
 constexpr int TR = 32;
 
 template <typename T>
@@ -421,13 +422,17 @@ __device__ __forceinline__ void transpose_block(int nx, int ny, const T *__restr
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void transpose_xy_kernel(int nx, int ny, const T *__restrict__ x,
+__global__ __launch_bounds__(256) void transpose_kernel(int nx, int ny, const T *__restrict__ x,
                                                            T *__restrict__ xt)
 {
     __shared__ T tile[TR][TR + 1];
     transpose_block<T>(nx, ny, x, xt, blockIdx.x, blockIdx.y, blockIdx.z, tile);
 }
 
+// The companion copy of a problem's trial point for its ray tile: for column
+// tiles the z-fastest copy, which is the transpose of x seen as an nz x
+// (ny nx) matrix (one slice of transpose_block); for row tiles the y-fastest
+// copy, one transpose per z slice.
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_grouped(BatchProblem<T> *probs, const int *offs,
                                                          int n)
@@ -438,9 +443,14 @@ __global__ __launch_bounds__(256) void transpose_grouped(BatchProblem<T> *probs,
     if (P.state != B_RUNNING)
         return;
     const int local = blockIdx.x - offs[p];
-    const int gx = (P.g.nx + TR - 1) / TR, gy = (P.g.ny + TR - 1) / TR;
-    transpose_block<T>(P.g.nx, P.g.ny, P.XB, P.XT, local % gx, (local / gx) % gy,
-                       local / (gx * gy), tile);
+    if (column_tiles(P.g.pj_wc)) {  // block-uniform
+        const int cols = P.g.nx * P.g.ny, gx = (cols + TR - 1) / TR;
+        transpose_block<T>(cols, P.g.nz, P.XB, P.XT, local % gx, local / gx, 0, tile);
+    } else {
+        const int gx = (P.g.nx + TR - 1) / TR, gy = (P.g.ny + TR - 1) / TR;
+        transpose_block<T>(P.g.nx, P.g.ny, P.XB, P.XT, local % gx, (local / gx) % gy,
+                           local / (gx * gy), tile);
+    }
 }
 
 // Batched UPN extrapolation after an accepted step (the control kernel has
@@ -723,10 +733,17 @@ hipError_t launch_bb_dots(int64_t n, const T *x, const T *xp, const T *g, const 
 }
 
 template <typename T>
-hipError_t launch_transpose_xy(int nx, int ny, int nz, const T *x, T *xt, hipStream_t st)
+hipError_t launch_companion(const GeomDev &g, const T *x, T *xc, hipStream_t st)
 {
-    dim3 grid((nx + TR - 1) / TR, (ny + TR - 1) / TR, nz);
-    hipLaunchKernelGGL((transpose_xy_kernel<T>), grid, dim3(256), 0, st, nx, ny, x, xt);
+    if (column_tiles(g.pj_wc)) {
+        // x as an nz x (ny nx) matrix, transposed
+        const int cols = g.nx * g.ny;
+        dim3 grid((cols + TR - 1) / TR, (g.nz + TR - 1) / TR, 1);
+        hipLaunchKernelGGL((transpose_kernel<T>), grid, dim3(256), 0, st, cols, g.nz, x, xc);
+    } else {
+        dim3 grid((g.nx + TR - 1) / TR, (g.ny + TR - 1) / TR, g.nz);
+        hipLaunchKernelGGL((transpose_kernel<T>), grid, dim3(256), 0, st, g.nx, g.ny, x, xc);
+    }
     return hipGetLastError();
 }
 
@@ -754,9 +771,11 @@ hipError_t launch_combine_phi(const double *r2, const double *tv, double alpha, 
     return hipGetLastError();
 }
 
-int transpose_blocks(int nx, int ny, int nz)
+int companion_blocks(const GeomDev &g)
 {
-    return ((nx + TR - 1) / TR) * ((ny + TR - 1) / TR) * nz;
+    if (column_tiles(g.pj_wc))
+        return ((g.nx * g.ny + TR - 1) / TR) * ((g.nz + TR - 1) / TR);
+    return ((g.nx + TR - 1) / TR) * ((g.ny + TR - 1) / TR) * g.nz;
 }
 
 template <typename T>
@@ -825,7 +844,7 @@ TVR_INST_GROUPED(double)
     template hipError_t launch_bb_dots<T>(int64_t, const T *, const T *, const T *, const T *,  \
                                           double *, int, hipStream_t, int *);                   \
     template hipError_t launch_clip<T>(int64_t, const T *, T *, Box, hipStream_t);              \
-    template hipError_t launch_transpose_xy<T>(int, int, int, const T *, T *, hipStream_t);
+    template hipError_t launch_companion<T>(const GeomDev &, const T *, T *, hipStream_t);
 
 TVR_INST(float)
 TVR_INST(double)

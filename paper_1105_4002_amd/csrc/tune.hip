@@ -14,11 +14,11 @@ using namespace tvr;
 
 namespace {
 
-constexpr int WC_SHAPES[4] = {8, 16, 32, 64};
+constexpr int WC_SHAPES[6] = {1, 2, 8, 16, 32, 64};
 constexpr int PJ_SHAPES[4] = {1, 2, 4, 8};
 constexpr int BP_SHAPES[3] = {4, 8, 16};
 
-bool valid_cols(int v) { return std::find(WC_SHAPES, WC_SHAPES + 4, v) != WC_SHAPES + 4; }
+bool valid_cols(int v) { return std::find(WC_SHAPES, WC_SHAPES + 6, v) != WC_SHAPES + 6; }
 bool valid_waves(int v) { return std::find(PJ_SHAPES, PJ_SHAPES + 4, v) != PJ_SHAPES + 4; }
 bool valid_depth(int v) { return std::find(BP_SHAPES, BP_SHAPES + 3, v) != BP_SHAPES + 3; }
 
@@ -71,7 +71,7 @@ tvreg_status tune_impl(tvreg_geometry *G, char *ws, int reps, tvreg_tuning *out,
     double best = INFINITY;
     t.project_tile_cols = G->g.pj_wc;
     t.project_waves = G->g.pj_ty;
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 6; ++a) {
         for (int i = 0; i < 4; ++i) {
             g.pj_wc = WC_SHAPES[a];
             g.pj_ty = PJ_SHAPES[i];
@@ -155,7 +155,7 @@ extern "C" tvreg_status tvreg_set_tuning(tvreg_geometry *G, const tvreg_tuning *
     if (!G || !t)
         return fail(TVREG_EINVAL, "NULL geometry or tuning");
     if (!valid_cols(t->project_tile_cols))
-        return fail(TVREG_EINVAL, "project_tile_cols must be 8, 16, 32 or 64, got %d",
+        return fail(TVREG_EINVAL, "project_tile_cols must be 1, 2, 8, 16, 32 or 64, got %d",
                     t->project_tile_cols);
     if (!valid_waves(t->project_waves))
         return fail(TVREG_EINVAL, "project_waves must be 1, 2, 4 or 8, got %d", t->project_waves);

@@ -108,7 +108,7 @@ struct GeomDev {
     MatDev mat;                // stored A^T when present
     int beam3d;                // 3D parallel beam: rays from v3, not from col / row
     const View3 *v3;           // [nviews] (3D parallel beam only)
-    int pj_wc;                 // projector: detector columns of a wave's ray tile (8, 16, 32, 64)
+    int pj_wc;                 // projector: detector columns of a wave's ray tile (1, 2, 8, 16, 32, 64)
     int pj_ty;                 // projector: ray tiles (waves) per block, stacked along rows (1, 2, 4, 8)
     int bp_cz;                 // on-the-fly backprojector: voxels per thread along z (4, 8, 16)
     int flat_row;              // cone: the detector row with w = 0 (invDz = 0), else -1
@@ -116,10 +116,18 @@ struct GeomDev {
     int sym_mir;               // turns (1, 2 or 4) and the z mirror (0 or 1)
 };
 
-// default tile shapes (the batched solve always uses these)
-constexpr int PJ_WC_DEFAULT = 64;
+// Default tile shapes.  The projector's default ray tile is two detector
+// columns x 32 rows where the detector has a multiple of 32 rows (no idle
+// lanes), else 64 columns x 1 row.
 constexpr int PJ_TY_DEFAULT = 4;
 constexpr int BP_CZ_DEFAULT = 8;
+inline int default_tile_cols(int rows) { return rows % 32 == 0 ? 2 : 64; }
+
+// The projector's companion copy of the volume (see launch_project): column
+// tiles (1 or 2 detector columns per wave) read a z-fastest copy
+// [y][x][z]; row tiles (8 or more columns) read the y-fastest copy [z][x][y]
+// for the views whose rays run mostly along x.
+__host__ __device__ inline bool column_tiles(int pj_wc) { return pj_wc <= 2; }
 
 // The feasible set Q = [lo, hi]^N (lo = 0, hi = +inf: the nonnegative
 // orthant) and its projection, a clip evaluated in double.
@@ -166,16 +174,18 @@ struct SlotList {
 // All return hipSuccess or the launch error.  `T` is float (FP32 storage with
 // FP64 reductions) or double.
 
-// out = A x (- b); xt, when not NULL, is the same volume stored y fastest
-// ([z][x][y]) and serves the views whose rays run mostly along x.
+// out = A x (- b); xt, when not NULL, is the companion copy of x for the
+// geometry's ray tile (launch_companion).  Without it the walk reads x
+// itself (the same values, at a lower rate).
 template <typename T>
 hipError_t launch_project(const GeomDev &g, const T *x, const T *xt, const T *b, T *out,
                           const T *rref, double *partials, int pstride, hipStream_t st,
                           int *nblocks);
 
-// xt[z][x][y] = x[z][y][x]
+// xc = the companion copy of x for the geometry's ray tile: xc[y][x][z] =
+// x[z][y][x] for column tiles, xc[z][x][y] = x[z][y][x] for row tiles
 template <typename T>
-hipError_t launch_transpose_xy(int nx, int ny, int nz, const T *x, T *xt, hipStream_t st);
+hipError_t launch_companion(const GeomDev &g, const T *x, T *xc, hipStream_t st);
 
 template <typename T>
 hipError_t launch_backproject(const GeomDev &g, const T *r, T *out, hipStream_t st);
@@ -261,7 +271,7 @@ int max_reduce_blocks_vol(int nx, int ny, int nz);
 int elementwise_blocks(int64_t n);
 int backproject_blocks(const GeomDev &g);
 int backproject_depth(const GeomDev &g);  // the geometry's voxel depth: 4, 8 or 16
-int transpose_blocks(int nx, int ny, int nz);
+int companion_blocks(const GeomDev &g);  // blocks of the grouped companion copy
 
 // ------------------------------------------------------------ batched solve
 // One problem of a batch, resident in device memory.  Every phase of a UPN /
@@ -309,9 +319,10 @@ hipError_t launch_trial_grouped(BatchProblem<T> *probs, const int *offs, int n, 
 template <typename T>
 hipError_t launch_transpose_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                                     hipStream_t st);
+// the problems whose ray tile is `cols` columns x `waves` waves per block
 template <typename T>
 hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
-                                  int waves, hipStream_t st);
+                                  int cols, int waves, hipStream_t st);
 template <typename T>
 hipError_t launch_extrapolate_grouped(BatchProblem<T> *probs, const int *offs, int n,
                                       int blocks, hipStream_t st);

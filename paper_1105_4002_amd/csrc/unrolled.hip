@@ -118,11 +118,11 @@ struct Unroller {
         return TVREG_OK;
     }
 
-    // out = A x (- b), with the y-fastest copy the projector reads
+    // out = A x (- b), with the companion copy the projector reads
     tvreg_status project(const T *x, const T *bb, T *out, const T *rref, int *nb)
     {
         const GeomDev &g = G->g;
-        TVR_HIP(launch_transpose_xy<T>(g.nx, g.ny, g.nz, x, fwdN(5), st));
+        TVR_HIP(launch_companion<T>(g, x, fwdN(5), st));
         TVR_HIP(launch_project<T>(g, x, fwdN(5), bb, out, rref, part, G->pstride, st, nb));
         return TVREG_OK;
     }

@@ -126,8 +126,8 @@ def test_batched_equals_single_solves(prec, poll):
 
 
 # (projector tile columns, waves per block, backprojector depth), one per
-# problem of mixed_problems(): every block shape and tile width appears
-TUNED_SHAPES = [(16, 2, 4), (8, 8, 16), (32, 1, 8), (64, 8, 4), (8, 1, 16), (64, 2, 4)]
+# problem of mixed_problems(): every block height and both tile kinds appear
+TUNED_SHAPES = [(1, 2, 4), (8, 8, 16), (2, 1, 8), (64, 8, 4), (16, 1, 16), (32, 2, 4)]
 
 
 @pytest.mark.parametrize("prec", [tv.F64, tv.F32])
