@@ -153,9 +153,14 @@ tvreg_status tvreg_backproject(const tvreg_geometry *geom, const void *r_dev, vo
  * for the cone beam with an even detector in both directions (no ray runs
  * inside a voxel face), view directions matching the turn to 1e-12, and
  * views, rows and columns that pack into 31 bits.  On by default.
- * tvreg_set_symmetry(geom, 0) keeps every voxel (the plain layout), 1 uses
- * the symmetry again; it must precede tvreg_matrix_plan / attach (EINVAL
- * while a transpose is attached).  tvreg_matrix_symmetry returns the number
+ * Without a stored transpose the on-the-fly backprojector uses the same
+ * group (no packing limit): one thread finds the rays and lengths of its
+ * cell voxels once per view and applies them to every image, so it does a
+ * fraction of the ray arithmetic; the identity image's sums are the plain
+ * gather's, bit for bit.
+ * tvreg_set_symmetry(geom, 0) keeps every voxel (the plain layout and the
+ * plain gather), 1 uses the symmetry again; it must precede
+ * tvreg_matrix_plan / attach (EINVAL while a transpose is attached).  tvreg_matrix_symmetry returns the number
  * of voxels one stored entry serves (1, 2, 4 or 8) for the attached
  * transpose or, before attaching, for the one tvreg_matrix_attach would
  * build.

@@ -247,8 +247,9 @@ class Geometry:
             self.handle = None
 
     def set_symmetry(self, use: bool) -> None:
-        """Whether a stored transpose uses the scan's symmetry
-        (tvreg_set_symmetry; on by default).  Not while a matrix is attached."""
+        """Whether a stored transpose and the on-the-fly backprojector use
+        the scan's symmetry (tvreg_set_symmetry; on by default).  Not while a
+        matrix is attached."""
         _check(_lib.tvreg_set_symmetry(self.handle, 1 if use else 0), "tvreg_set_symmetry")
 
     def attach_matrix(self, device="cuda", symmetric: bool = True) -> int:

@@ -710,17 +710,20 @@ struct Solver {
             run.add(S_RD2, nb);
         return TVREG_OK;
     }
-    // g = A^T r + alpha grad T(y); slots of T(y) and, with xref, the Bregman terms
+    // g = A^T r + alpha grad T(y); the slot of T(y) (GPBB's objective values
+    // only) and, with xref, the Bregman terms
     tvreg_status gradient(const T *y, const T *ry, const T *xref, T *g)
     {
         TVR_HIP(run.timed(TVREG_KERNEL_BACKPROJECT,
                           [&] { return launch_backproject<T>(G->g, ry, g, run.st); }));
         int nb = 0;
+        const bool value = p->method == TVREG_GPBB;
         TVR_HIP(run.timed(TVREG_KERNEL_TV, [&] {
             return launch_tv<T>(nx, ny, nz, p->tau, p->alpha, y, xref, g, g, run.part,
-                                run.pstride, run.st, &nb);
+                                run.pstride, run.st, &nb, value);
         }));
-        run.add(S_TVY, nb);
+        if (value)
+            run.add(S_TVY, nb);
         if (xref) {
             run.add(S_BRY, nb);
             run.add(S_XY2, nb);

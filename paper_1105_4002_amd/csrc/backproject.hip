@@ -279,6 +279,257 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
     }
 }
 
+// ------------------------------------------------------------ symmetric scan
+// A circular cone scan with the quarter-turn (or half-turn) symmetry and / or
+// the z mirror of GeomDev sym_rot / sym_mir (the group the stored transpose
+// uses): the rays through the image of voxel j under q turns, in view
+// v + q V / ROT, are the rays through j in view v, with the same lengths, and
+// the rays through its mirror image z -> -z are those of the mirrored
+// detector rows R - 1 - row, with the same |D|.  A thread of the symmetric
+// gather owns a voxel column of the cell the images tile the volume from
+// (the stored transpose's cell), finds its rays and lengths once per view,
+// and applies them to all NI = ROT (x 2 with the mirror) images, reading
+// each image's detector tile -- the rotated views, the mirrored rows --
+// from LDS.  Each image sums its views in the order v + q V / ROT, v = 0 ..
+// V - 1 (the identity image: the plain gather's order and values).
+constexpr int STILE_R = 16;  // detector rows the symmetric gather stages per view
+
+template <typename T, int NI>
+struct SymTile {
+    T rt[NI][(STILE_R + 1) * TILE_S];   // each image's r, [row - R0][col - C0]; row STILE_R: 0
+    double dt[(STILE_R + 1) * TILE_S];  // |D| of the cell's rays; row STILE_R: 0
+    double Sx[TILE_C], Sy[TILE_C], iDx[TILE_C], iDy[TILE_C], ox[TILE_C], oy[TILE_C];
+    double iDz[STILE_R + 1];
+};
+
+// Global-memory source of one image for views whose footprint exceeds the
+// tile: the cell's ray entries of view v, image data of view vq with rows
+// mirrored when MIRROR.
+template <typename T, bool MIRROR>
+struct SymGlobalSrc {
+    const GeomDev *g;
+    const ColEntry *colv;  // view v's column entries
+    const T *rq;           // view vq's data
+    __device__ ColEntry column(int c) const { return colv[c]; }
+    __device__ double Sz(int r) const { return g->row[r].Sz; }
+    __device__ double invDz(int r) const { return g->row[r].invDz; }
+    __device__ double oz_(int r) const { return g->row[r].oz; }
+    __device__ double value(int r, int c) const
+    {
+        const int rm = MIRROR ? g->rows - 1 - r : r;
+        return (double)rq[(size_t)rm * g->cols + c] * g->dnorm[(size_t)r * g->cols + c];
+    }
+};
+
+template <bool FLAT, int NI, int CZ, typename T>
+__device__ __forceinline__ void sym_row(const SymTile<T, NI> &S, int rel, int cc, double Z0,
+                                        double Z1, double tl, double th, double flat_len, bool ok,
+                                        double (&acc)[NI][CZ], int k)
+{
+    const int o = (ok ? rel : STILE_R) * TILE_S + cc;
+    const double idz = S.iDz[ok ? rel : STILE_R];
+    const double t0 = Z0 * idz, t1 = Z1 * idz;
+    const double lo = fmax(tl, fmin(t0, t1)), hi = fmin(th, fmax(t0, t1));
+    double len = hi - lo;
+    if (FLAT)
+        len = idz != 0.0 ? len : flat_len;
+    len = fmax(len, 0.0);
+    const double dn = S.dt[o];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+        acc[i][k] = fma(len, (double)S.rt[i][o] * dn, acc[i][k]);
+}
+
+// The cone-beam gather of gather_cone_tile for the cell's voxels iz0 ..
+// iz0 + CZ - 1 below mz, every ray applied to the NI images.
+template <int CZ, bool FLAT, int NI, typename T>
+__device__ __forceinline__ void gather_cone_sym(const GeomDev &g, const SymTile<T, NI> &S,
+                                                double c, double s, double X0, double X1,
+                                                double Y0, double Y1, int iz0, int mz, int C0,
+                                                int C1, int R0, int R1, double (&acc)[NI][CZ])
+{
+    double f0, f1, bmin, bmax;
+    u_footprint<true>(g, c, s, X0, X1, Y0, Y1, f0, f1, bmin, bmax);
+    int c_lo, c_hi;
+    index_range(f0, f1, C0, C1, c_lo, c_hi);
+    const double row_lo_off = g.rv0 - (double)R0 - 1e-6, row_hi_off = g.rv0 - (double)R0 + 1e-6;
+    const double row_last = (double)(R1 - R0);
+    for (int col = c_lo; col <= c_hi; ++col) {
+        const int cc = col - C0;
+        double tl, th;
+        xy_interval<true>(X0, X1, Y0, Y1, S.Sx[cc], S.Sy[cc], S.iDx[cc], S.iDy[cc], S.ox[cc],
+                          S.oy[cc], tl, th);
+        if (!(th > tl))
+            continue;
+        const double itl = rcp(tl) * g.ipv, ith = rcp(th) * g.ipv;
+        double Z0 = -g.hz + (double)iz0;
+        double qa = Z0 * itl, qb = Z0 * ith;
+#pragma unroll
+        for (int k = 0; k < CZ; ++k) {
+            const double Z1 = Z0 + 1.0;
+            const double pa = Z1 * itl, pb = Z1 * ith;
+            if (iz0 + k < mz) {  // block-uniform
+                const int lo = (int)fmax(ceil(fmin(qa, qb) + row_lo_off), 0.0);
+                const int hi = (int)fmin(floor(fmax(pa, pb) + row_hi_off), row_last);
+                const double fl = FLAT && Z0 <= 0.0 && 0.0 < Z1 ? th - tl : 0.0;
+                sym_row<FLAT>(S, lo, cc, Z0, Z1, tl, th, fl, lo <= hi, acc, k);
+                sym_row<FLAT>(S, lo + 1, cc, Z0, Z1, tl, th, fl, lo + 1 <= hi, acc, k);
+                for (int rel = lo + 2; rel <= hi; ++rel)  // wide footprints only
+                    sym_row<FLAT>(S, rel, cc, Z0, Z1, tl, th, fl, true, acc, k);
+            }
+            Z0 = Z1;
+            qa = pa;
+            qb = pb;
+        }
+    }
+}
+
+// cell of the symmetric gather (the stored transpose's cell)
+__host__ __device__ __forceinline__ void sym_cell(const GeomDev &g, int &mx, int &my, int &mz)
+{
+    mx = g.sym_rot == 4 ? g.nx / 2 : g.nx;
+    my = g.sym_rot >= 2 ? g.ny / 2 : g.ny;
+    mz = g.sym_mir ? g.nz / 2 : g.nz;
+}
+
+// One block of the symmetric gather: BP_TX x BP_TY voxel columns of the
+// cell, CZ voxels deep, block (bx, by, bz) of the cell.
+template <typename T, int ROT, bool MIR, int CZ>
+__device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T *__restrict__ r,
+                                                      T *__restrict__ out, int bx, int by, int bz,
+                                                      SymTile<T, ROT *(MIR ? 2 : 1)> &S)
+{
+    constexpr int NM = MIR ? 2 : 1, NI = ROT * NM;
+    int mx, my, mz;
+    sym_cell(g, mx, my, mz);
+    const int tid = threadIdx.x;
+    const int ix = bx * BP_TX + (tid % BP_TX);
+    const int iy = by * BP_TY + (tid / BP_TX);
+    const int iz0 = bz * CZ;
+    const bool active = ix < mx && iy < my;  // the others stage data and meet every barrier
+
+    double acc[NI][CZ];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int k = 0; k < CZ; ++k)
+            acc[i][k] = 0.0;
+
+    const double X0 = -g.hx + (double)ix, X1 = X0 + 1.0;
+    const double Y0 = -g.hy + (double)iy, Y1 = Y0 + 1.0;
+    const double bX0 = -g.hx + (double)(bx * BP_TX);
+    const double bY0 = -g.hy + (double)(by * BP_TY);
+    const double bZ0 = -g.hz + (double)iz0;
+    const double bX1 = fmin(bX0 + BP_TX, -g.hx + mx), bY1 = fmin(bY0 + BP_TY, -g.hy + my);
+    const double bZ1 = fmin(bZ0 + CZ, -g.hz + mz);
+    const size_t view_stride = (size_t)g.rows * g.cols;
+    const int vstep = g.nviews / ROT;
+    for (int i = tid; i < TILE_S; i += BP_THREADS) {  // the zero rows
+        S.dt[STILE_R * TILE_S + i] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NI; ++q)
+            S.rt[q][STILE_R * TILE_S + i] = T(0);
+    }
+    if (tid == 0)
+        S.iDz[STILE_R] = 1.0;
+
+    for (int v = 0; v < g.nviews; ++v) {
+        const double c = g.cs[v].x, s = g.cs[v].y;
+        double f0, f1, bmin, bmax;
+        u_footprint<true>(g, c, s, bX0, bX1, bY0, bY1, f0, f1, bmin, bmax);
+        int C0, C1, R0, R1;
+        index_range(f0, f1, 0, g.cols - 1, C0, C1);
+        const double i0 = g.SDD * rcp(g.R - bmin), i1 = g.SDD * rcp(g.R - bmax);
+        const double wlo = fmin(bZ0 * i0, bZ0 * i1), whi = fmax(bZ1 * i0, bZ1 * i1);
+        index_range(wlo * g.ipv + g.rv0, whi * g.ipv + g.rv0, 0, g.rows - 1, R0, R1);
+        const int nc = C1 - C0 + 1, nr = R1 - R0 + 1;
+        if (nc <= 0 || nr <= 0)
+            continue;  // block-uniform
+        if (nc <= TILE_C && nr <= STILE_R) {
+            for (int i = tid; i < nr * nc; i += BP_THREADS) {
+                const int rr = i / nc, cc = i - rr * nc;
+                const int row = R0 + rr, col = C0 + cc;
+                const int o = rr * TILE_S + cc;
+                S.dt[o] = g.dnorm[(size_t)row * g.cols + col];
+                int vq = v;
+#pragma unroll
+                for (int q = 0; q < ROT; ++q) {
+                    const T *rq = r + (size_t)vq * view_stride;
+                    S.rt[q * NM][o] = rq[(size_t)row * g.cols + col];
+                    if (MIR)
+                        S.rt[q * NM + 1][o] = rq[(size_t)(g.rows - 1 - row) * g.cols + col];
+                    vq += vstep;
+                    vq -= vq >= g.nviews ? g.nviews : 0;
+                }
+            }
+            for (int i = tid; i < nc; i += BP_THREADS) {
+                const ColEntry e = g.col[(size_t)v * g.cols + C0 + i];
+                S.Sx[i] = e.Sx;
+                S.Sy[i] = e.Sy;
+                S.iDx[i] = e.invDx;
+                S.iDy[i] = e.invDy;
+                S.ox[i] = e.ox;
+                S.oy[i] = e.oy;
+            }
+            for (int i = tid; i < nr; i += BP_THREADS)
+                S.iDz[i] = g.row[R0 + i].invDz;
+            __syncthreads();
+            if (active) {
+                if (g.flat_row >= R0 && g.flat_row <= R1)  // block-uniform
+                    gather_cone_sym<CZ, true>(g, S, c, s, X0, X1, Y0, Y1, iz0, mz, C0, C1, R0,
+                                              R1, acc);
+                else
+                    gather_cone_sym<CZ, false>(g, S, c, s, X0, X1, Y0, Y1, iz0, mz, C0, C1, R0,
+                                               R1, acc);
+            }
+            __syncthreads();
+        } else if (active) {  // the generic arithmetic, image by image
+            const ColEntry *colv = g.col + (size_t)v * g.cols;
+            int vq = v;
+#pragma unroll
+            for (int q = 0; q < ROT; ++q) {
+                const T *rq = r + (size_t)vq * view_stride;
+                const SymGlobalSrc<T, false> src{&g, colv, rq};
+                gather_view<true, CZ>(g, src, c, s, X0, X1, Y0, Y1, iz0, 0, g.cols - 1, 0,
+                                      g.rows - 1, acc[q * NM]);
+                if (MIR) {
+                    const SymGlobalSrc<T, true> srm{&g, colv, rq};
+                    gather_view<true, CZ>(g, srm, c, s, X0, X1, Y0, Y1, iz0, 0, g.cols - 1, 0,
+                                          g.rows - 1, acc[q * NM + NM - 1]);
+                }
+                vq += vstep;
+                vq -= vq >= g.nviews ? g.nviews : 0;
+            }
+        }
+    }
+
+    if (!active)
+        return;
+    const size_t plane = (size_t)g.nx * g.ny;
+    int xi = ix, yi = iy;
+#pragma unroll
+    for (int q = 0; q < ROT; ++q) {
+#pragma unroll
+        for (int k = 0; k < CZ; ++k) {
+            const int iz = iz0 + k;
+            if (iz < mz) {
+                out[(size_t)iz * plane + (size_t)yi * g.nx + xi] = (T)acc[q * NM][k];
+                if (MIR)
+                    out[(size_t)(g.nz - 1 - iz) * plane + (size_t)yi * g.nx + xi] =
+                        (T)acc[q * NM + 1][k];
+            }
+        }
+        if (ROT == 4) {  // a quarter turn: (i, j) -> (nx - 1 - j, i)
+            const int t = xi;
+            xi = g.nx - 1 - yi;
+            yi = t;
+        } else if (ROT == 2) {  // a half turn: (i, j) -> (nx - 1 - i, ny - 1 - j)
+            xi = g.nx - 1 - xi;
+            yi = g.ny - 1 - yi;
+        }
+    }
+}
+
 // The hardware deals consecutive blocks round-robin to the 8 XCDs, each with
 // its own L2; the kernel remaps block ids so that each XCD runs a contiguous
 // range of bricks (x fastest, then y, then z): its L2 then serves the
@@ -299,6 +550,23 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_kernel(GeomDev g,
         backproject_block3d<T, CZ>(g, r, out, L % gx, (L / gx) % gy, L / (gx * gy));
     else
         backproject_block<T, CONE, CZ>(g, r, out, L % gx, (L / gx) % gy, L / (gx * gy), tile);
+}
+
+// The symmetric gather (see backproject_sym_block), block ids remapped to
+// XCD-contiguous ranges as in backproject_kernel.
+template <typename T, int ROT, bool MIR, int CZ>
+__global__ __launch_bounds__(BP_THREADS) void backproject_sym_kernel(GeomDev g,
+                                                                    const T *__restrict__ r,
+                                                                    T *__restrict__ out)
+{
+    __shared__ SymTile<T, ROT *(MIR ? 2 : 1)> S;
+    const int nb = gridDim.x, p = blockIdx.x;
+    const int q = nb / N_XCD, rem = nb % N_XCD, k = p % N_XCD;
+    const int L = k * q + min(k, rem) + p / N_XCD;
+    int mx, my, mz;
+    sym_cell(g, mx, my, mz);
+    const int gx = (mx + BP_TX - 1) / BP_TX, gy = (my + BP_TY - 1) / BP_TY;
+    backproject_sym_block<T, ROT, MIR, CZ>(g, r, out, L % gx, (L / gx) % gy, L / (gx * gy), S);
 }
 
 // Batched: G = A^T RY for every problem whose gradient is due this round.
@@ -330,6 +598,25 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_grouped(BatchProblem<T
     backproject_grouped_body<T, CZ>(P, blockIdx.x - offs[p], tile);
 }
 
+// Batched symmetric gather: the problems whose scan has the symmetry
+// (ROT, MIR), each block one block of its problem's cell.
+template <typename T, int ROT, bool MIR, int CZ>
+__global__ __launch_bounds__(BP_THREADS) void backproject_sym_grouped(BatchProblem<T> *probs,
+                                                                     const int *offs, int n)
+{
+    __shared__ SymTile<T, ROT *(MIR ? 2 : 1)> S;
+    const int p = find_problem(offs, n, blockIdx.x);
+    const BatchProblem<T> &P = probs[p];
+    if (P.state != B_RUNNING || !P.need_grad)
+        return;
+    const int local = blockIdx.x - offs[p];
+    int mx, my, mz;
+    sym_cell(P.g, mx, my, mz);
+    const int gx = (mx + BP_TX - 1) / BP_TX, gy = (my + BP_TY - 1) / BP_TY;
+    backproject_sym_block<T, ROT, MIR, CZ>(P.g, P.RY, P.G, local % gx, (local / gx) % gy,
+                                           local / (gx * gy), S);
+}
+
 }  // namespace
 
 int backproject_depth(const GeomDev &g) { return g.bp_cz == 4 || g.bp_cz == 16 ? g.bp_cz : 8; }
@@ -340,6 +627,50 @@ int backproject_blocks(const GeomDev &g)
     const int cz = backproject_depth(g);
     return ((g.nx + BP_TX - 1) / BP_TX) * ((g.ny + BP_TY - 1) / BP_TY) * ((g.nz + cz - 1) / cz);
 }
+
+bool backproject_symmetric(const GeomDev &g)
+{
+    return g.cone && !g.beam3d && (g.sym_rot > 1 || g.sym_mir);
+}
+
+// voxels per thread of the symmetric gather: 16 accumulators per thread
+constexpr int sym_depth(int rot, int mir) { return 16 / (rot * (mir ? 2 : 1)); }
+
+int backproject_sym_blocks(const GeomDev &g)
+{
+    int mx, my, mz;
+    sym_cell(g, mx, my, mz);
+    const int cz = sym_depth(g.sym_rot, g.sym_mir);
+    return ((mx + BP_TX - 1) / BP_TX) * ((my + BP_TY - 1) / BP_TY) * ((mz + cz - 1) / cz);
+}
+
+template <typename T>
+hipError_t launch_backproject_sym_grouped(BatchProblem<T> *probs, const int *offs, int n,
+                                          int blocks, int rot, int mir, hipStream_t st)
+{
+    const dim3 gr(blocks), bl(BP_THREADS);
+    if (rot == 4 && mir)
+        hipLaunchKernelGGL((backproject_sym_grouped<T, 4, true, sym_depth(4, 1)>), gr, bl, 0, st,
+                           probs, offs, n);
+    else if (rot == 4)
+        hipLaunchKernelGGL((backproject_sym_grouped<T, 4, false, sym_depth(4, 0)>), gr, bl, 0,
+                           st, probs, offs, n);
+    else if (rot == 2 && mir)
+        hipLaunchKernelGGL((backproject_sym_grouped<T, 2, true, sym_depth(2, 1)>), gr, bl, 0, st,
+                           probs, offs, n);
+    else if (rot == 2)
+        hipLaunchKernelGGL((backproject_sym_grouped<T, 2, false, sym_depth(2, 0)>), gr, bl, 0,
+                           st, probs, offs, n);
+    else
+        hipLaunchKernelGGL((backproject_sym_grouped<T, 1, true, sym_depth(1, 1)>), gr, bl, 0, st,
+                           probs, offs, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_backproject_sym_grouped<float>(BatchProblem<float> *, const int *,
+                                                          int, int, int, int, hipStream_t);
+template hipError_t launch_backproject_sym_grouped<double>(BatchProblem<double> *, const int *,
+                                                           int, int, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_backproject_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
@@ -372,11 +703,29 @@ static void launch_backproject_cz(const GeomDev &g, const T *r, T *out, hipStrea
         hipLaunchKernelGGL((backproject_kernel<T, false, CZ>), grid, block, 0, st, g, r, out);
 }
 
+template <typename T, int ROT, bool MIR>
+static void launch_backproject_sym(const GeomDev &g, const T *r, T *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((backproject_sym_kernel<T, ROT, MIR, sym_depth(ROT, MIR)>),
+                       dim3(backproject_sym_blocks(g)), dim3(BP_THREADS), 0, st, g, r, out);
+}
+
 template <typename T>
 hipError_t launch_backproject(const GeomDev &g, const T *r, T *out, hipStream_t st)
 {
     if (g.mat.present)
         return launch_backproject_matrix<T>(g, r, out, st);
+    if (backproject_symmetric(g)) {
+        if (g.sym_rot == 4)
+            g.sym_mir ? launch_backproject_sym<T, 4, true>(g, r, out, st)
+                      : launch_backproject_sym<T, 4, false>(g, r, out, st);
+        else if (g.sym_rot == 2)
+            g.sym_mir ? launch_backproject_sym<T, 2, true>(g, r, out, st)
+                      : launch_backproject_sym<T, 2, false>(g, r, out, st);
+        else
+            launch_backproject_sym<T, 1, true>(g, r, out, st);
+        return hipGetLastError();
+    }
     switch (g.bp_cz) {
     case 4:
         launch_backproject_cz<T, 4>(g, r, out, st);

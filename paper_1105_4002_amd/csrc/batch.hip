@@ -159,10 +159,15 @@ namespace {
 // F_BP8) and the projector one per ray tile (6 widths x 4 block heights,
 // from F_PJ), so that every problem runs its own tuned tiles, each family in
 // a kernel compiled for that shape alone.
+// Problems whose scan has a symmetry take the symmetric gather, one family
+// per group (turns, mirror): F_BPS .. F_BPS + 4.
 constexpr int PJ_FAMILY_WC[6] = {1, 2, 8, 16, 32, 64};
 constexpr int PJ_FAMILY_TY[4] = {1, 2, 4, 8};
 constexpr int N_PJ = 24;
-enum Family : int { F_BP4 = 0, F_BP8, F_SP, F_VOX, F_TR, F_EX, F_PJ, F_COUNT = F_PJ + N_PJ };
+constexpr int BPS_ROT[5] = {4, 4, 2, 2, 1}, BPS_MIR[5] = {1, 0, 1, 0, 1};
+enum Family : int {
+    F_BP4 = 0, F_BP8, F_BPS, F_SP = F_BPS + 5, F_VOX, F_TR, F_EX, F_PJ, F_COUNT = F_PJ + N_PJ
+};
 constexpr int BP_FAMILY_CZ[2] = {4, 8};
 
 // Per-problem region: X, XB, YB, G, XT (N values each), RX, RXB, RYB (m
@@ -233,9 +238,14 @@ int family_blocks(const tvreg_geometry *G, int f)
     const GeomDev g = batch_shapes(G->g);
     if (f >= F_PJ)
         return pj_family(g) == f ? project_blocks(g) : 0;
+    const bool sym = !g.mat.present && backproject_symmetric(g);
     if (f >= F_BP4 && f <= F_BP8)
-        return !g.mat.present && backproject_depth(g) == BP_FAMILY_CZ[f - F_BP4]
+        return !g.mat.present && !sym && backproject_depth(g) == BP_FAMILY_CZ[f - F_BP4]
                    ? backproject_blocks(g)
+                   : 0;
+    if (f >= F_BPS && f < F_BPS + 5)
+        return sym && g.sym_rot == BPS_ROT[f - F_BPS] && g.sym_mir == BPS_MIR[f - F_BPS]
+                   ? backproject_sym_blocks(g)
                    : 0;
     switch (f) {
     case F_SP:
@@ -364,6 +374,10 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         if (le == hipSuccess && total[f] > 0)
             le = launch_backproject_grouped<T>(dprobs, fam(f), n, total[f],
                                                BP_FAMILY_CZ[f - F_BP4], cs);
+    for (int f = F_BPS; f < F_BPS + 5; ++f)
+        if (le == hipSuccess && total[f] > 0)
+            le = launch_backproject_sym_grouped<T>(dprobs, fam(f), n, total[f],
+                                                   BPS_ROT[f - F_BPS], BPS_MIR[f - F_BPS], cs);
     if (le == hipSuccess && total[F_SP] > 0)
         le = launch_spmv_grouped<T>(dprobs, fam(F_SP), n, total[F_SP], cs);
     if (le == hipSuccess)

@@ -121,7 +121,7 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
                                          const T *__restrict__ y, const T *__restrict__ xref,
                                          const T *__restrict__ gin, T *__restrict__ gout,
                                          double *__restrict__ partials, int pstride, int bx,
-                                         int by, int bz, int bid)
+                                         int by, int bz, int bid, bool value)
 {
     __shared__ T ys[2][VY + 2][VX + 2];  // x in [x0 - 1, x0 + VX], y in [y0 - 1, y0 + VY]
     __shared__ T xs[2][VY + 1][VX + 1];  // x in [x0, x0 + VX], y in [y0, y0 + VY]
@@ -207,7 +207,8 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
                 gout[j] = gin ? (T)((double)gin_cur + alpha * (double)gsum)
                               : (T)(alpha * (double)gsum);
             if (partials) {
-                red[0] += (double)huber_c<T>(d2, ct, itau);
+                if (value)
+                    red[0] += (double)huber_c<T>(d2, ct, itau);
                 if (xref) {
                     const T(&X)[VY + 1][VX + 1] = xs[cur];
                     const T xj = X[ty][tx];
@@ -233,9 +234,13 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
         }
         cur = nxt;
     }
-    if (partials) {
+    if (partials && value) {
         const int slots[3] = {S_TVY, S_BRY, S_XY2};
         block_reduce_store<3>(red, partials, pstride, slots, bid);
+    } else if (partials && xref) {  // the Bregman terms only
+        const int slots[2] = {S_BRY, S_XY2};
+        double r2[2] = {red[1], red[2]};
+        block_reduce_store<2>(r2, partials, pstride, slots, bid);
     }
 }
 
@@ -245,10 +250,11 @@ __global__ __launch_bounds__(VX *VY) void tv_kernel(int nx, int ny, int nz, doub
                                                     const T *__restrict__ xref,
                                                     const T *__restrict__ gin,
                                                     T *__restrict__ gout,
-                                                    double *__restrict__ partials, int pstride)
+                                                    double *__restrict__ partials, int pstride,
+                                                    bool value)
 {
     tv_block<T>(nx, ny, nz, tau, alpha, y, xref, gin, gout, partials, pstride, blockIdx.x,
-                blockIdx.y, blockIdx.z, block_linear_id());
+                blockIdx.y, blockIdx.z, block_linear_id(), value);
 }
 
 // local block -> (bx, by, bz) of a voxel grid
@@ -262,7 +268,8 @@ __device__ __forceinline__ void voxel_block_coords(int local, int nx, int ny, in
 }
 
 // Batched gradient assembly G += alpha grad T(Y), with the Bregman terms
-// against X once Y has moved away from X.
+// against X once Y has moved away from X (UPN, the batched method, needs no
+// value of T(Y)).
 template <typename T>
 __global__ __launch_bounds__(VX *VY) void tv_grouped(BatchProblem<T> *probs, const int *offs,
                                                      int n)
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(VX *VY) void tv_grouped(BatchProblem<T> *probs, con
     int bx, by, bz;
     voxel_block_coords(local, P.g.nx, P.g.ny, bx, by, bz);
     tv_block<T>(P.g.nx, P.g.ny, P.g.nz, P.tau, P.alpha, P.Y, P.distinct ? P.X : nullptr, P.G,
-                P.G, P.part, P.pstride, bx, by, bz, local);
+                P.G, P.part, P.pstride, bx, by, bz, local, false);
 }
 
 template <typename T>
@@ -524,9 +531,9 @@ __device__ __forceinline__ double fixed_order_sum(const double *__restrict__ src
 
 // Batched finaliser: one block per (problem, slot) of the slots the round
 // produced.
-constexpr int NFIN = 10;
+constexpr int NFIN = 9;
 __constant__ const int fin_slots[NFIN] = {S_XD2, S_GD, S_TVB, S_BRB, S_R2, S_RD2,
-                                          S_TVY, S_BRY, S_XY2, S_RY2};
+                                          S_BRY, S_XY2, S_RY2};
 
 template <typename T>
 __global__ __launch_bounds__(FB) void finalize_grouped(BatchProblem<T> *probs)
@@ -539,7 +546,7 @@ __global__ __launch_bounds__(FB) void finalize_grouped(BatchProblem<T> *probs)
     int count;
     if (slot == S_R2 || slot == S_RD2)
         count = P.nb_proj;
-    else if (slot == S_TVY || slot == S_BRY || slot == S_XY2)
+    else if (slot == S_BRY || slot == S_XY2)
         count = P.need_grad ? P.nb_vox : 0;
     else if (slot == S_RY2)
         count = P.ry2_pending ? P.nb_ew : 0;
@@ -673,13 +680,13 @@ int max_reduce_blocks_vol(int nx, int ny, int nz)
 template <typename T>
 hipError_t launch_tv(int nx, int ny, int nz, double tau, double alpha, const T *y, const T *xref,
                      const T *gin, T *gout, double *partials, int pstride, hipStream_t st,
-                     int *nblocks)
+                     int *nblocks, bool value)
 {
     const dim3 gr = voxel_grid(nx, ny, nz);
     if (nblocks)
         *nblocks = (int)(gr.x * gr.y * gr.z);
     hipLaunchKernelGGL((tv_kernel<T>), gr, dim3(VX, VY), 0, st, nx, ny, nz, tau, alpha, y, xref,
-                       gin, gout, partials, pstride);
+                       gin, gout, partials, pstride, value);
     return hipGetLastError();
 }
 
@@ -833,7 +840,7 @@ TVR_INST_GROUPED(double)
 
 #define TVR_INST(T)                                                                              \
     template hipError_t launch_tv<T>(int, int, int, double, double, const T *, const T *,       \
-                                     const T *, T *, double *, int, hipStream_t, int *);        \
+                                     const T *, T *, double *, int, hipStream_t, int *, bool);        \
     template hipError_t launch_trial<T>(int, int, int, double, const T *, const T *, double,     \
                                         double, Box, T *, double *, int, hipStream_t, int *);   \
     template hipError_t launch_extrapolate<T>(int64_t, double, const T *, const T *, T *,       \

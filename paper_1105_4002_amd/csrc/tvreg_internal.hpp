@@ -190,12 +190,12 @@ hipError_t launch_companion(const GeomDev &g, const T *x, T *xc, hipStream_t st)
 template <typename T>
 hipError_t launch_backproject(const GeomDev &g, const T *r, T *out, hipStream_t st);
 
-// gout = (gin ? gin + alpha * grad T(y) : grad T(y)); slots S_TVY and, with
-// xref, S_BRY and S_XY2.  gout may be NULL (value only).
+// gout = (gin ? gin + alpha * grad T(y) : grad T(y)); slots S_TVY (with
+// `value`) and, with xref, S_BRY and S_XY2.  gout may be NULL (value only).
 template <typename T>
 hipError_t launch_tv(int nx, int ny, int nz, double tau, double alpha, const T *y, const T *xref,
                      const T *gin, T *gout, double *partials, int pstride, hipStream_t st,
-                     int *nblocks);
+                     int *nblocks, bool value = true);
 
 // xbar = P_Q(z - step g); slots S_XD2, S_GD, S_TVB, S_BRB and (gm_step > 0) S_GM2.
 template <typename T>
@@ -271,6 +271,10 @@ int max_reduce_blocks_vol(int nx, int ny, int nz);
 int elementwise_blocks(int64_t n);
 int backproject_blocks(const GeomDev &g);
 int backproject_depth(const GeomDev &g);  // the geometry's voxel depth: 4, 8 or 16
+// Whether the on-the-fly backprojector gathers through the scan's symmetry
+// (cone beam with GeomDev sym_rot > 1 or sym_mir), and its blocks.
+bool backproject_symmetric(const GeomDev &g);
+int backproject_sym_blocks(const GeomDev &g);
 int companion_blocks(const GeomDev &g);  // blocks of the grouped companion copy
 
 // ------------------------------------------------------------ batched solve
@@ -305,7 +309,11 @@ struct BatchProblem {
 template <typename T>
 hipError_t launch_backproject_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                                       int depth, hipStream_t st);
-// the problems with a stored transpose (the on-the-fly kernel above takes the others)
+// the problems whose on-the-fly gather uses the scan's symmetry (rot, mir)
+template <typename T>
+hipError_t launch_backproject_sym_grouped(BatchProblem<T> *probs, const int *offs, int n,
+                                          int blocks, int rot, int mir, hipStream_t st);
+// the problems with a stored transpose (the on-the-fly kernels above take the others)
 template <typename T>
 hipError_t launch_spmv_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                                hipStream_t st);

@@ -50,6 +50,8 @@ def mixed_problems():
         (synth.Geometry(6, 9, 7, np.array([0.4, 1.7, 3.3, 5.0]), synth.CONE, 16, 11, 1.3, 1.2,
                         30.0, 50.0), 16,
          dict(method=tv.UPN, alpha=1e-2, eps=1e-8, max_iter=60), "signed"),    # clipped start
+        (synth.cone_geometry(12, 8, 18, 16, 1.5, 48.0, 72.0), 17,
+         dict(method=tv.UPN, alpha=1e-2, eps=1e-6, max_iter=80), "zero"),      # quarter turns + mirror
     ]
 
 
@@ -127,7 +129,8 @@ def test_batched_equals_single_solves(prec, poll):
 
 # (projector tile columns, waves per block, backprojector depth), one per
 # problem of mixed_problems(): every block height and both tile kinds appear
-TUNED_SHAPES = [(1, 2, 4), (8, 8, 16), (2, 1, 8), (64, 8, 4), (16, 1, 16), (32, 2, 4)]
+TUNED_SHAPES = [(1, 2, 4), (8, 8, 16), (2, 1, 8), (64, 8, 4), (16, 1, 16), (32, 2, 4),
+                (2, 4, 8)]
 
 
 @pytest.mark.parametrize("prec", [tv.F64, tv.F32])
