@@ -5,15 +5,16 @@ Workload (synthetic, seeded): 256^3 voxels, cone beam with 60 views over
 360 degrees, flat detector 384 x 256 at pitch 1.5, source 1024 and detector
 1536 from the centre, 24-ellipsoid phantom, 0.5 % Gaussian noise,
 alpha = 3e-3, tau = 1e-4.  Method: UPN (Alg. 3) with FP32 vectors and FP64
-reductions; the backprojector streams the stored voxel-major A^T (built
-before the timed region, its size and build time reported), the projector
-walks the rays on the fly.
+reductions; the projector walks the rays on the fly; the backprojector is
+the faster of the stored voxel-major A^T's product (built before the timed
+region, its size and build time reported) and the on-the-fly gather through
+the scan's symmetry, timed on the workload first (the choice is reported).
 
 A "step" is one UPN iteration: gradient at y (backprojection + TV stencil),
 projected trial step(s) with the projector's fused residual, the scalar
 control and the extrapolation.  `value` is gradient evaluations per second
 over exactly --steps iterations (inputs resident in HBM).  Beside it: the
-same rate with every operator on the fly; the time to a 1e-6 relative
+same rate with the other backprojector; the time to a 1e-6 relative
 gradient-map tolerance from x0 = 0 for UPN in FP32 and in FP64 (the metric's
 two halves, their ratio, and the FP32 result's distance to the FP64 one),
 and for GP in FP64 (the paper's plain method in plain precision; capped in
@@ -49,17 +50,12 @@ HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 # x 1).  An entry is reported only while the text of its source files is the
 # one measured, and the projector's only at the measured ray tile
 # (profiles/cone256_kernels_hbm_traffic_pmc.md).
-MEASURED_TRAFFIC = {
-    # project_kernel<float, cone, 64 columns, 4 waves>: 639945 + 25655.5 KiB
-    "project": {"sources": ["paper_1105_4002_amd/csrc/project.hip",
-                            "paper_1105_4002_amd/csrc/raywalk.hpp"],
-                "sha256_prefix": "37baf7e8b0c07c3f", "stored": None, "tile": (64, 4),
-                "bytes": (2 * 639945.0 + 25655.5) * 1024},
+MEASURED_TRAFFIC = [
     # spmv_sym_kernel<float, quarter turns, z mirror>: 814996.4 + 77781.3 KiB
-    "backproject": {"sources": ["paper_1105_4002_amd/csrc/matrix.hip"],
-                    "sha256_prefix": "80160ee1be1d8553", "stored": True, "tile": None,
-                    "bytes": (2 * 814996.4 + 77781.3) * 1024},
-}
+    {"kernel": "backproject", "stored": True, "tile": None,
+     "sources": ["paper_1105_4002_amd/csrc/matrix.hip"], "sha256_prefix": "80160ee1be1d8553",
+     "bytes": (2 * 814996.4 + 77781.3) * 1024},
+]
 
 
 def sources_sha(paths) -> str:
@@ -72,16 +68,17 @@ def sources_sha(paths) -> str:
 
 
 def measured_traffic(kernel: str, stored: bool, tile=None):
-    """GB per launch measured for `kernel`, or None when there is no
-    measurement for this form of it (or its source has changed since)."""
-    e = MEASURED_TRAFFIC.get(kernel)
-    if e is None or (e["stored"] is not None and e["stored"] != stored):
-        return None
-    if e["tile"] is not None and tuple(tile or ()) != e["tile"]:
-        return None
-    if not sources_sha(e["sources"]).startswith(e["sha256_prefix"]):
-        return None
-    return round(e["bytes"] / 1e9, 3)
+    """GB per launch measured for `kernel` in this form (backprojector from
+    the stored A^T or on the fly; the projector's ray tile), or None when
+    there is no such measurement or its sources have changed since."""
+    for e in MEASURED_TRAFFIC:
+        if e["kernel"] != kernel or (e["stored"] is not None and e["stored"] != stored):
+            continue
+        if e["tile"] is not None and tuple(tile or ()) != e["tile"]:
+            continue
+        if sources_sha(e["sources"]).startswith(e["sha256_prefix"]):
+            return round(e["bytes"] / 1e9, 3)
+    return None
 
 
 FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed math)
@@ -109,17 +106,15 @@ def kernel_model(name: str, N: int, m: int, nnz: int, es: int, stored: bool):
     vector is read (x for A, r for A^T), served by the caches or HBM.  The
     projector walks its rays on the fly and is held by instruction issue: its
     work is its vector instructions (PROJECT_VALU_PER_STEP per voxel step)
-    against the issue rate.  The backprojector streams the stored A^T; its
-    work is the gather model of the product, es per non-zero (the value of r
-    it reads) plus the volume written and the residual's compulsory read."""
+    against the issue rate.  The backprojector, streaming the stored A^T or
+    gathering on the fly, is rated on the gather model of the product: es
+    per non-zero (the value of r it reads) plus the volume written and the
+    residual's compulsory read."""
     if name == "project":
         return "alu", PROJECT_VALU_PER_STEP * float(nnz), "T lane-instr/s", VALU_ISSUE_PEAK
     if name == "backproject":
-        if stored:
-            return "hbm", es * float(nnz) + 2.0 * es * N, "GB/s", HBM_PEAK
-        # 10 flops per (voxel, ray) pair: two z-plane parameters (2 FMA),
-        # max, min, length, |D| scale, accumulate (FMA)
-        return "alu", 10.0 * nnz, "TFLOP/s", FP64_VEC_PEAK
+        # both forms (stored A^T, on-the-fly gather) against the gather model
+        return "hbm", es * float(nnz) + 2.0 * es * N, "GB/s", HBM_PEAK
     if name == "tv":
         return "hbm", es * 4.0 * N, "GB/s", HBM_PEAK       # y, x_ref, g in, g out
     if name == "trial":
@@ -634,6 +629,33 @@ def main() -> int:
                                                      4)}
         log(f"  {tuning}")
 
+    choice = None
+    if stored:
+        # the headline takes the faster backprojector: the stored A^T's
+        # product or the on-the-fly gather (through the scan's symmetry)
+        rr = torch.randn(w.geom.proj_shape, device=dev).float()
+        times = {}
+        for form in ("stored", "on_the_fly"):
+            if form == "on_the_fly":
+                G32.detach_matrix()
+            xb = tv.backproject(G32, rr)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                tv.backproject(G32, rr, out=xb)
+            e1.record()
+            e1.synchronize()
+            times[form] = e0.elapsed_time(e1) / 10
+        del rr, xb
+        stored = times["stored"] < times["on_the_fly"]
+        if stored:
+            G32.attach_matrix()
+        choice = {"stored_ms": round(times["stored"], 4),
+                  "on_the_fly_ms": round(times["on_the_fly"], 4),
+                  "chosen": "stored" if stored else "on_the_fly"}
+        log(f"backprojector: {choice}")
+
     log(f"warmup: {args.warmup} UPN iterations")
     xw, iw, _ = tv.solve(G32, b32, method=tv.UPN, eps=0.0, max_iter=max(args.warmup, 1),
                          workspace=ws32, **common)
@@ -711,13 +733,17 @@ def main() -> int:
                                "384x256 @1.5, R=1024, SDD=1536, 24 ellipsoids, 0.5% noise, "
                                "alpha=3e-3, tau=1e-4; UPN, FP32 vectors + FP64 reductions",
                    "operators": ("projector on the fly, backprojector from the stored A^T"
-                                 if stored else "both on the fly"),
+                                 if stored else
+                                 "both on the fly (the backprojector through the scan's "
+                                 "symmetry)"),
                    "global_batch": 1, "parallelism": "single GPU"},
         "roofline": roofline,
         "kernels": kernels,
     }
     if matrix:
         result["stored_transpose"] = matrix
+    if choice:
+        result["backprojector"] = choice
     if tuning:
         result["tuning"] = tuning
     result["hbm_copy_GBps"] = round(copy_gbs, 1)
@@ -730,18 +756,26 @@ def main() -> int:
         result["grad_eval_graph"] = grad_eval_graph(tv, torch, G32, b32, x_true.float(), w)
         log(f"  {result['grad_eval_graph']}")
 
-    if stored and not args.no_legs:
-        log(f"same solve with every operator on the fly: {args.steps} UPN iterations")
-        G32.detach_matrix()
+    if matrix and not args.no_legs:
+        # the same solve with the other backprojector
+        other = "on_the_fly" if stored else "with_stored_transpose"
+        log(f"same solve {other.replace('_', ' ')}: {args.steps} UPN iterations")
+        if stored:
+            G32.detach_matrix()
+        else:
+            G32.attach_matrix()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, i0, _ = tv.solve(G32, b32, method=tv.UPN, eps=0.0, max_iter=args.steps, x0=xw,
                             L_bar=iw["L"], workspace=ws32, **common)
         torch.cuda.synchronize()
         d0 = time.perf_counter() - t0
-        result["on_the_fly"] = {"value": round(i0["grad_evals"] / d0, 3),
-                                "ms_per_step": round(1e3 * d0 / args.steps, 4)}
-        G32.attach_matrix()
+        result[other] = {"value": round(i0["grad_evals"] / d0, 3),
+                         "ms_per_step": round(1e3 * d0 / args.steps, 4)}
+        if stored:
+            G32.attach_matrix()
+        else:
+            G32.detach_matrix()
 
     x_tol = {}
     if not args.no_tol:

@@ -290,14 +290,14 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
 // (the stored transpose's cell), finds its rays and lengths once per view,
 // and applies them to all NI = ROT (x 2 with the mirror) images, reading
 // each image's detector tile -- the rotated views, the mirrored rows --
-// from LDS.  Each image sums its views in the order v + q V / ROT, v = 0 ..
-// V - 1 (the identity image: the plain gather's order and values).
+// from LDS (r |D| in double, as the plain gather stages it).  Each image
+// sums its views in the order v + q V / ROT, v = 0 .. V - 1 (the identity
+// image: the plain gather's order and values).
 constexpr int STILE_R = 16;  // detector rows the symmetric gather stages per view
 
-template <typename T, int NI>
+template <int NI>
 struct SymTile {
-    T rt[NI][(STILE_R + 1) * TILE_S];   // each image's r, [row - R0][col - C0]; row STILE_R: 0
-    double dt[(STILE_R + 1) * TILE_S];  // |D| of the cell's rays; row STILE_R: 0
+    double rt[NI][(STILE_R + 1) * TILE_S];  // each image's r |D|, [row - R0][col - C0]; row STILE_R: 0
     double Sx[TILE_C], Sy[TILE_C], iDx[TILE_C], iDy[TILE_C], ox[TILE_C], oy[TILE_C];
     double iDz[STILE_R + 1];
 };
@@ -321,8 +321,8 @@ struct SymGlobalSrc {
     }
 };
 
-template <bool FLAT, int NI, int CZ, typename T>
-__device__ __forceinline__ void sym_row(const SymTile<T, NI> &S, int rel, int cc, double Z0,
+template <bool FLAT, int NI, int CZ>
+__device__ __forceinline__ void sym_row(const SymTile<NI> &S, int rel, int cc, double Z0,
                                         double Z1, double tl, double th, double flat_len, bool ok,
                                         double (&acc)[NI][CZ], int k)
 {
@@ -334,16 +334,15 @@ __device__ __forceinline__ void sym_row(const SymTile<T, NI> &S, int rel, int cc
     if (FLAT)
         len = idz != 0.0 ? len : flat_len;
     len = fmax(len, 0.0);
-    const double dn = S.dt[o];
 #pragma unroll
     for (int i = 0; i < NI; ++i)
-        acc[i][k] = fma(len, (double)S.rt[i][o] * dn, acc[i][k]);
+        acc[i][k] = fma(len, S.rt[i][o], acc[i][k]);
 }
 
 // The cone-beam gather of gather_cone_tile for the cell's voxels iz0 ..
 // iz0 + CZ - 1 below mz, every ray applied to the NI images.
-template <int CZ, bool FLAT, int NI, typename T>
-__device__ __forceinline__ void gather_cone_sym(const GeomDev &g, const SymTile<T, NI> &S,
+template <int CZ, bool FLAT, int NI>
+__device__ __forceinline__ void gather_cone_sym(const GeomDev &g, const SymTile<NI> &S,
                                                 double c, double s, double X0, double X1,
                                                 double Y0, double Y1, int iz0, int mz, int C0,
                                                 int C1, int R0, int R1, double (&acc)[NI][CZ])
@@ -397,7 +396,7 @@ __host__ __device__ __forceinline__ void sym_cell(const GeomDev &g, int &mx, int
 template <typename T, int ROT, bool MIR, int CZ>
 __device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T *__restrict__ r,
                                                       T *__restrict__ out, int bx, int by, int bz,
-                                                      SymTile<T, ROT *(MIR ? 2 : 1)> &S)
+                                                      SymTile<ROT *(MIR ? 2 : 1)> &S)
 {
     constexpr int NM = MIR ? 2 : 1, NI = ROT * NM;
     int mx, my, mz;
@@ -425,10 +424,9 @@ __device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T 
     const size_t view_stride = (size_t)g.rows * g.cols;
     const int vstep = g.nviews / ROT;
     for (int i = tid; i < TILE_S; i += BP_THREADS) {  // the zero rows
-        S.dt[STILE_R * TILE_S + i] = 0.0;
 #pragma unroll
         for (int q = 0; q < NI; ++q)
-            S.rt[q][STILE_R * TILE_S + i] = T(0);
+            S.rt[q][STILE_R * TILE_S + i] = 0.0;
     }
     if (tid == 0)
         S.iDz[STILE_R] = 1.0;
@@ -450,14 +448,16 @@ __device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T 
                 const int rr = i / nc, cc = i - rr * nc;
                 const int row = R0 + rr, col = C0 + cc;
                 const int o = rr * TILE_S + cc;
-                S.dt[o] = g.dnorm[(size_t)row * g.cols + col];
+                // |D| of a mirrored row is that of the row (rows symmetric about w = 0)
+                const double dn = g.dnorm[(size_t)row * g.cols + col];
                 int vq = v;
 #pragma unroll
                 for (int q = 0; q < ROT; ++q) {
                     const T *rq = r + (size_t)vq * view_stride;
-                    S.rt[q * NM][o] = rq[(size_t)row * g.cols + col];
+                    S.rt[q * NM][o] = (double)rq[(size_t)row * g.cols + col] * dn;
                     if (MIR)
-                        S.rt[q * NM + 1][o] = rq[(size_t)(g.rows - 1 - row) * g.cols + col];
+                        S.rt[q * NM + 1][o] =
+                            (double)rq[(size_t)(g.rows - 1 - row) * g.cols + col] * dn;
                     vq += vstep;
                     vq -= vq >= g.nviews ? g.nviews : 0;
                 }
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(BP_THREADS) void backproject_sym_kernel(GeomDev g,
                                                                     const T *__restrict__ r,
                                                                     T *__restrict__ out)
 {
-    __shared__ SymTile<T, ROT *(MIR ? 2 : 1)> S;
+    __shared__ SymTile<ROT *(MIR ? 2 : 1)> S;
     const int nb = gridDim.x, p = blockIdx.x;
     const int q = nb / N_XCD, rem = nb % N_XCD, k = p % N_XCD;
     const int L = k * q + min(k, rem) + p / N_XCD;
@@ -604,7 +604,7 @@ template <typename T, int ROT, bool MIR, int CZ>
 __global__ __launch_bounds__(BP_THREADS) void backproject_sym_grouped(BatchProblem<T> *probs,
                                                                      const int *offs, int n)
 {
-    __shared__ SymTile<T, ROT *(MIR ? 2 : 1)> S;
+    __shared__ SymTile<ROT *(MIR ? 2 : 1)> S;
     const int p = find_problem(offs, n, blockIdx.x);
     const BatchProblem<T> &P = probs[p];
     if (P.state != B_RUNNING || !P.need_grad)
@@ -633,8 +633,9 @@ bool backproject_symmetric(const GeomDev &g)
     return g.cone && !g.beam3d && (g.sym_rot > 1 || g.sym_mir);
 }
 
-// voxels per thread of the symmetric gather: 16 accumulators per thread
-constexpr int sym_depth(int rot, int mir) { return 16 / (rot * (mir ? 2 : 1)); }
+// voxels per thread of the symmetric gather: 32 accumulators per thread, at
+// most 8 voxels deep
+constexpr int sym_depth(int rot, int mir) { return rot * (mir ? 2 : 1) >= 4 ? 32 / (rot * (mir ? 2 : 1)) : 8; }
 
 int backproject_sym_blocks(const GeomDev &g)
 {

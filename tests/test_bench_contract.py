@@ -42,25 +42,27 @@ def test_kernel_models_are_positive_and_bounded():
 
 def test_measured_traffic_is_tied_to_the_kernel_text():
     """Each measured figure is reported only for the form it was measured on
-    (projector at its ray tile, the stored product only with a stored A^T)
-    and only while its sources hash to the measured text."""
+    (the backprojector from the stored A^T or on the fly, the projector at
+    its ray tile) and only while its sources hash to the measured text."""
     b = load_bench()
-    for name, e in b.MEASURED_TRAFFIC.items():
+    forms = [(e["kernel"], e["stored"], e["tile"]) for e in b.MEASURED_TRAFFIC]
+    assert forms and len(set(forms)) == len(forms)
+    assert b.measured_traffic("tv", True) is None
+    for e in b.MEASURED_TRAFFIC:
         assert e["bytes"] > 0 and len(e["sha256_prefix"]) == 16
         for p in e["sources"]:
             assert os.path.isfile(os.path.join(ROOT, p))
-    assert b.measured_traffic("tv", True) is None
-    assert b.measured_traffic("backproject", False) is None
-    assert b.measured_traffic("project", True, (8, 8)) is None
-    e = b.MEASURED_TRAFFIC["project"]
-    current = b.sources_sha(e["sources"]).startswith(e["sha256_prefix"])
-    got = b.measured_traffic("project", True, e["tile"])
-    assert (got is not None) == current
-    if got is not None:
-        assert got == round(e["bytes"] / 1e9, 3)
-    saved = e["sha256_prefix"]
-    try:
-        e["sha256_prefix"] = "0" * 16
-        assert b.measured_traffic("project", True, e["tile"]) is None
-    finally:
-        e["sha256_prefix"] = saved
+        stored = True if e["stored"] is None else e["stored"]
+        current = b.sources_sha(e["sources"]).startswith(e["sha256_prefix"])
+        got = b.measured_traffic(e["kernel"], stored, e["tile"])
+        assert got == (round(e["bytes"] / 1e9, 3) if current else None)
+        if e["tile"] is not None:
+            assert b.measured_traffic(e["kernel"], stored, (3, 3)) is None
+        if e["stored"] is not None and (e["kernel"], not e["stored"], e["tile"]) not in forms:
+            assert b.measured_traffic(e["kernel"], not e["stored"], e["tile"]) is None
+        saved = e["sha256_prefix"]
+        try:
+            e["sha256_prefix"] = "0" * 16
+            assert b.measured_traffic(e["kernel"], stored, e["tile"]) is None
+        finally:
+            e["sha256_prefix"] = saved
