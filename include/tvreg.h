@@ -103,6 +103,16 @@ void tvreg_destroy_geometry(tvreg_geometry *geom);
  */
 tvreg_status tvreg_project(const tvreg_geometry *geom, const void *x_dev, void *y_dev,
                            void *stream);
+/*
+ * The same y = A x as the solvers project: the companion copy of x for the
+ * geometry's ray tile (see the tile shapes below) is written to ws_dev
+ * (tvreg_project_workspace_bytes: N values of T) and the walk reads it, at
+ * the solvers' rate.  Equal to tvreg_project's y bit for bit.  ENOMEM for a
+ * short workspace.
+ */
+size_t tvreg_project_workspace_bytes(const tvreg_geometry *geom);
+tvreg_status tvreg_project_ws(const tvreg_geometry *geom, const void *x_dev, void *y_dev,
+                              void *ws_dev, size_t ws_bytes, void *stream);
 
 /*
  * x = A^T r  (the data part of grad phi, Sec. III-A eq. 6 needs grad f).

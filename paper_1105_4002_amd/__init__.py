@@ -71,7 +71,7 @@ class _SolveInfo(ctypes.Structure):
 
 # Every symbol include/tvreg.h declares.
 EXPORTS = ("tvreg_create_geometry", "tvreg_destroy_geometry", "tvreg_project",
-           "tvreg_backproject", "tvreg_matrix_scratch_bytes", "tvreg_matrix_plan",
+           "tvreg_project_workspace_bytes", "tvreg_project_ws", "tvreg_backproject", "tvreg_matrix_scratch_bytes", "tvreg_matrix_plan",
            "tvreg_matrix_attach", "tvreg_matrix_detach", "tvreg_set_symmetry",
            "tvreg_matrix_symmetry", "tvreg_autotune_workspace_bytes",
            "tvreg_autotune", "tvreg_get_tuning", "tvreg_set_tuning", "tvreg_tv_workspace_bytes",
@@ -99,6 +99,10 @@ def _load():
     L.tvreg_destroy_geometry.restype = None
     L.tvreg_project.argtypes = [vp, vp, vp, vp]
     L.tvreg_project.restype = st
+    L.tvreg_project_workspace_bytes.argtypes = [vp]
+    L.tvreg_project_workspace_bytes.restype = sz
+    L.tvreg_project_ws.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.tvreg_project_ws.restype = st
     L.tvreg_backproject.argtypes = [vp, vp, vp, vp]
     L.tvreg_backproject.restype = st
     L.tvreg_matrix_scratch_bytes.argtypes = [vp]
@@ -322,12 +326,25 @@ class Geometry:
         return torch.empty(self.proj_shape, dtype=self.dtype, device=device)
 
 
-def project(geom: Geometry, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """y = A x (tvreg_project)."""
+def project(geom: Geometry, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+            workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A x (tvreg_project); with a workspace (project_workspace) the
+    solvers' form through the companion copy (tvreg_project_ws)."""
     y = geom.empty_data(x.device) if out is None else out
-    _check(_lib.tvreg_project(geom.handle, _ptr(x, geom.dtype, geom.N, "x"),
-                              _ptr(y, geom.dtype, geom.m, "y"), _stream(x)), "tvreg_project")
+    if workspace is None:
+        _check(_lib.tvreg_project(geom.handle, _ptr(x, geom.dtype, geom.N, "x"),
+                                  _ptr(y, geom.dtype, geom.m, "y"), _stream(x)), "tvreg_project")
+    else:
+        _check(_lib.tvreg_project_ws(geom.handle, _ptr(x, geom.dtype, geom.N, "x"),
+                                     _ptr(y, geom.dtype, geom.m, "y"), workspace.data_ptr(),
+                                     workspace.numel() * workspace.element_size(), _stream(x)),
+               "tvreg_project_ws")
     return y
+
+
+def project_workspace(geom: Geometry, device="cuda") -> torch.Tensor:
+    return torch.empty(_lib.tvreg_project_workspace_bytes(geom.handle), dtype=torch.uint8,
+                       device=device)
 
 
 def backproject(geom: Geometry, r: torch.Tensor, out: Optional[torch.Tensor] = None):

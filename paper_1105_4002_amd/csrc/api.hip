@@ -349,6 +349,36 @@ extern "C" tvreg_status tvreg_project(const tvreg_geometry *G, const void *x, vo
     return TVREG_OK;
 }
 
+extern "C" size_t tvreg_project_workspace_bytes(const tvreg_geometry *G)
+{
+    return G ? elem_size(G->prec) * (size_t)G->N : 0;
+}
+
+extern "C" tvreg_status tvreg_project_ws(const tvreg_geometry *G, const void *x, void *y,
+                                         void *ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    if (!G || !x || !y || !ws)
+        return fail(TVREG_EINVAL, "NULL geometry or buffer");
+    if (ws_bytes < tvreg_project_workspace_bytes(G))
+        return fail(TVREG_ENOMEM, "workspace of %zu bytes needed",
+                    tvreg_project_workspace_bytes(G));
+    DeviceGuard dg(G->device);
+    if (!dg.ok)
+        return fail(TVREG_EDEVICE, "cannot select device %d", G->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (G->prec == TVREG_F64) {
+        TVR_HIP(launch_companion<double>(G->g, (const double *)x, (double *)ws, st));
+        TVR_HIP((launch_project<double>(G->g, (const double *)x, (const double *)ws, nullptr,
+                                        (double *)y, nullptr, nullptr, 0, st, nullptr)));
+    } else {
+        TVR_HIP(launch_companion<float>(G->g, (const float *)x, (float *)ws, st));
+        TVR_HIP((launch_project<float>(G->g, (const float *)x, (const float *)ws, nullptr,
+                                       (float *)y, nullptr, nullptr, 0, st, nullptr)));
+    }
+    return TVREG_OK;
+}
+
 extern "C" tvreg_status tvreg_backproject(const tvreg_geometry *G, const void *r, void *x,
                                           void *stream)
 {

@@ -12,6 +12,8 @@ symmetry group stored, every entry applied to all images of its voxel).
   differ from the directly computed ones only by the rounding of the view
   angles' cosines).
 * The FP64 solver takes the oracle's steps with it.
+* The solvers' projection through the companion copy equals the plain
+  projection bit for bit (and so the oracle's).
 * The on-the-fly backprojector gathers through the same symmetry (no stored
   transpose): its products match the oracle at the operator bar and the
   plain gather within 1e-13 of the output scale, and on the cell the images
@@ -227,6 +229,60 @@ def test_symmetric_gather_solver_first_iterations_match_oracle_fp64():
                               max_iter=K, hist_len=K, bt_form=1)
     G = tv.Geometry(g, tv.F64)
     assert tv.lib().tvreg_matrix_symmetry(G.handle) == 4  # the group the gather uses
+    x, info, h = tv.solve(G, to_dev(b, tv.F64), method=tv.UPN, alpha=1e-2, tau=1e-4, eps=0.0,
+                          max_iter=K, hist_len=K)
+    assert info["iters"] == io["iters"]
+    np.testing.assert_array_equal(np.array(h["L"]), ho["L"][:K])
+    assert np.max(np.abs(host(x) - xo)) <= 1e-9 * max(np.max(np.abs(xo)), 1.0)
+
+
+
+@pytest.mark.parametrize("cols", [1, 2, 64])
+@pytest.mark.parametrize("prec", [tv.F64, tv.F32])
+@pytest.mark.parametrize("name", ["quarter_mirror", "half_odd_nz", "mirror_only", "odd_rows"])
+def test_companion_projection_matches_plain_and_oracle(name, prec, cols):
+    """The solvers' projection (tvreg_project_ws: the companion copy of the
+    tile) is tvreg_project's bit for bit, and the oracle's at the operator
+    bar."""
+    g, _ = CASES[name]
+    print(f"companion projection {name} prec={prec} cols={cols}", flush=True)
+    G = tv.Geometry(g, prec)
+    G.set_tuning(cols, 4, 8)
+    x = rounded(synth.random_volume(g.vol_shape, 65), prec)
+    got = host(tv.project(G, to_dev(x, prec), workspace=tv.project_workspace(G)))
+    np.testing.assert_array_equal(got, host(tv.project(G, to_dev(x, prec))))
+    ref = oracle.project(g, x)
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    if prec == tv.F64:
+        assert np.max(np.abs(got - ref)) <= 1e-12 * scale
+    else:
+        tol = 2.0 ** -24 * np.abs(ref) + 1e-9 * scale
+        assert not (np.abs(got - ref) > tol).any()
+
+
+def test_project_ws_rejects_short_workspace():
+    g, _ = CASES["quarter_mirror"]
+    G = tv.Geometry(g, tv.F32)
+    x = to_dev(np.zeros(g.vol_shape), tv.F32)
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(tv.TvregError) as e:
+        tv.project(G, x, workspace=ws)
+    assert e.value.status == tv.ENOMEM
+
+
+@pytest.mark.parametrize("name", ["quarter_mirror", "half_mirror", "mirror_only"])
+def test_column_tile_solver_first_iterations_match_oracle_fp64(name):
+    """25 UPN steps with column tiles (z-fastest companion) and the symmetric
+    gather take the oracle's steps."""
+    g, _ = CASES[name]
+    og = oracle.Geometry(g)
+    b = oracle.noisy_data(og, synth.random_volume(g.vol_shape, 66),
+                          synth.unit_noise(og.proj_shape, 67), 0.01)
+    K = 25
+    xo, io, ho = oracle.solve(og, b, method=oracle.UPN, alpha=1e-2, tau=1e-4, eps=0.0,
+                              max_iter=K, hist_len=K, bt_form=1)
+    G = tv.Geometry(g, tv.F64)
+    G.set_tuning(2, 4, 8)
     x, info, h = tv.solve(G, to_dev(b, tv.F64), method=tv.UPN, alpha=1e-2, tau=1e-4, eps=0.0,
                           max_iter=K, hist_len=K)
     assert info["iters"] == io["iters"]
