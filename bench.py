@@ -517,7 +517,10 @@ def main() -> int:
                          "seconds (0: no limit)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-matrix", action="store_true",
-                    help="evaluate A^T on the fly in the headline solve")
+                    help="evaluate A^T on the fly in the headline solve (no stored A^T built)")
+    ap.add_argument("--backprojector", choices=("auto", "stored", "on_the_fly"), default="auto",
+                    help="the headline's backprojector: the faster of the two on the workload "
+                         "(auto), or the one named")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the on-the-fly, batch and differentiated legs")
     ap.add_argument("--batch-seq", action="store_true",
@@ -595,7 +598,7 @@ def main() -> int:
     torch.cuda.synchronize()
     ws32 = tv.solve_workspace(G32, tv.UPN)
     common = dict(alpha=w.alpha, tau=w.tau)
-    stored = not args.no_matrix
+    stored = not args.no_matrix and args.backprojector != "on_the_fly"
     matrix = None
     if stored:
         log("building the stored A^T")
@@ -648,12 +651,13 @@ def main() -> int:
             e1.synchronize()
             times[form] = e0.elapsed_time(e1) / 10
         del rr, xb
-        stored = times["stored"] < times["on_the_fly"]
+        stored = (times["stored"] < times["on_the_fly"] if args.backprojector == "auto"
+                  else args.backprojector == "stored")
         if stored:
             G32.attach_matrix()
         choice = {"stored_ms": round(times["stored"], 4),
                   "on_the_fly_ms": round(times["on_the_fly"], 4),
-                  "chosen": "stored" if stored else "on_the_fly"}
+                  "chosen": "stored" if stored else "on_the_fly", "rule": args.backprojector}
         log(f"backprojector: {choice}")
 
     log(f"warmup: {args.warmup} UPN iterations")
