@@ -294,11 +294,13 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
 // sums its views in the order v + q V / ROT, v = 0 .. V - 1 (the identity
 // image: the plain gather's order and values).
 constexpr int STILE_R = 16;  // detector rows the symmetric gather stages per view
+constexpr int STILE_C = 48;  // ... and columns
+constexpr int STILE_S = STILE_C + 1;  // odd row stride (in doubles)
 
 template <int NI>
 struct SymTile {
-    double rt[NI][(STILE_R + 1) * TILE_S];  // each image's r |D|, [row - R0][col - C0]; row STILE_R: 0
-    double Sx[TILE_C], Sy[TILE_C], iDx[TILE_C], iDy[TILE_C], ox[TILE_C], oy[TILE_C];
+    double rt[NI][(STILE_R + 1) * STILE_S];  // each image's r |D|, [row - R0][col - C0]; row STILE_R: 0
+    double Sx[STILE_C], Sy[STILE_C], iDx[STILE_C], iDy[STILE_C], ox[STILE_C], oy[STILE_C];
     double iDz[STILE_R + 1];
 };
 
@@ -326,7 +328,7 @@ __device__ __forceinline__ void sym_row(const SymTile<NI> &S, int rel, int cc, d
                                         double Z1, double tl, double th, double flat_len, bool ok,
                                         double (&acc)[NI][CZ], int k)
 {
-    const int o = (ok ? rel : STILE_R) * TILE_S + cc;
+    const int o = (ok ? rel : STILE_R) * STILE_S + cc;
     const double idz = S.iDz[ok ? rel : STILE_R];
     const double t0 = Z0 * idz, t1 = Z1 * idz;
     const double lo = fmax(tl, fmin(t0, t1)), hi = fmin(th, fmax(t0, t1));
@@ -423,10 +425,10 @@ __device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T 
     const double bZ1 = fmin(bZ0 + CZ, -g.hz + mz);
     const size_t view_stride = (size_t)g.rows * g.cols;
     const int vstep = g.nviews / ROT;
-    for (int i = tid; i < TILE_S; i += BP_THREADS) {  // the zero rows
+    for (int i = tid; i < STILE_S; i += BP_THREADS) {  // the zero rows
 #pragma unroll
         for (int q = 0; q < NI; ++q)
-            S.rt[q][STILE_R * TILE_S + i] = 0.0;
+            S.rt[q][STILE_R * STILE_S + i] = 0.0;
     }
     if (tid == 0)
         S.iDz[STILE_R] = 1.0;
@@ -443,11 +445,11 @@ __device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T 
         const int nc = C1 - C0 + 1, nr = R1 - R0 + 1;
         if (nc <= 0 || nr <= 0)
             continue;  // block-uniform
-        if (nc <= TILE_C && nr <= STILE_R) {
+        if (nc <= STILE_C && nr <= STILE_R) {
             for (int i = tid; i < nr * nc; i += BP_THREADS) {
                 const int rr = i / nc, cc = i - rr * nc;
                 const int row = R0 + rr, col = C0 + cc;
-                const int o = rr * TILE_S + cc;
+                const int o = rr * STILE_S + cc;
                 // |D| of a mirrored row is that of the row (rows symmetric about w = 0)
                 const double dn = g.dnorm[(size_t)row * g.cols + col];
                 int vq = v;

@@ -1,7 +1,9 @@
 """Full-size parity on the 256^3 cone-beam scan (60 views of 384 x 256), in
-the launch configuration the benchmark times: FP32 vectors with FP64 sums,
-the stored A^T, and tile shapes chosen by the autotuner.  The data b comes
-from the oracle (its projection of the phantom plus the seeded noise).
+the launch configurations the benchmark times: FP32 vectors with FP64 sums,
+tile shapes chosen by the autotuner, and the backprojector either on the fly
+through the scan's symmetry (the headline's) or from the stored A^T.  The
+data b comes from the oracle (its projection of the phantom plus the seeded
+noise).
 
 * phi and grad phi at the phantom against the oracle's FP64 evaluation at the
   same FP32 values: phi within 1e-6 relative; every gradient element within
@@ -32,13 +34,19 @@ DEV = "cuda"
 
 
 @pytest.fixture(scope="module")
-def scan():
+def data():
     w = synth.cfg_cone256()
     print("cone256: oracle data", flush=True)
-    b = oracle.noisy_data(w.geom, w.phantom(), w.unit_noise(), w.eta)
+    return w, oracle.noisy_data(w.geom, w.phantom(), w.unit_noise(), w.eta)
+
+
+@pytest.fixture(scope="module", params=["on_the_fly", "stored"])
+def scan(request, data):
+    w, b = data
     G = tv.Geometry(w.geom, tv.F32)
-    print("cone256: stored A^T and autotune", flush=True)
-    G.attach_matrix()
+    print(f"cone256: backprojector {request.param}; autotune", flush=True)
+    if request.param == "stored":
+        G.attach_matrix()
     t = G.autotune(reps=2)
     print(f"cone256: tuned {G.tuning}, projector {t['project_ms'][t['project_tile_cols'], t['project_waves']]:.3f} ms",
           flush=True)
@@ -59,8 +67,8 @@ def test_cone256_objective_grad_matches_oracle(scan):
     print("cone256: oracle phi / grad", flush=True)
     phi_ref, g_ref = oracle.phi_grad(w.geom, b, w.alpha, w.tau, x)
     assert abs(float(phi.item()) - phi_ref) <= 1e-6 * abs(phi_ref)
-    # data part A^T r: r rounded once to FP32, the stored values rounded once,
-    # the sum in double; the output rounded once
+    # data part A^T r: r rounded once to FP32, the stored values (if any)
+    # rounded once, the sum in double; the output rounded once
     r = oracle.project(w.geom, x) - b.reshape(w.geom.proj_shape)
     data_bound = oracle.backproject(w.geom, np.abs(r))
     scale = np.max(np.abs(g_ref))
