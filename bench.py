@@ -99,10 +99,10 @@ VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s
 # gfx950 code the build emits for project_kernel on volumes under 2 GiB, the
 # same for the 2 x 32 and 64 x 1 ray tiles: 3 min and 1 compare for the
 # segment end; decrement and compare of the iteration bound; 3 compares, 3
-# selects and 2 adds for the index; 3 high-word selects, 1 move of the zero
-# low word, 3 adds and 3 FMAs for the planes and next crossings; length,
-# move, 32-bit load offset, convert and accumulate)
-PROJECT_VALU_PER_STEP = 29
+# selects and 2 adds for the byte offset; 3 high-word selects, 1 move of the
+# zero low word, 3 adds and 3 FMAs for the planes and next crossings; length,
+# move, convert and accumulate)
+PROJECT_VALU_PER_STEP = 28
 
 
 def log(msg: str) -> None:

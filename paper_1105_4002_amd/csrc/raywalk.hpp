@@ -135,18 +135,19 @@ __device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry 
 // format, no swizzle).
 constexpr int BUF_WORD3 = 0x00020000;
 
+// (`off` in bytes: the walk then keeps its index in bytes, with no scaling per step)
 template <typename T>
-__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned idx);
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
 template <>
-__device__ __forceinline__ double buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned idx)
+__device__ __forceinline__ double buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off)
 {
-    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(idx * 4u), 0, 0);
+    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
     return (double)__builtin_bit_cast(float, v);
 }
 template <>
-__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned idx)
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(idx * 8u), 0, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
 // Sum of dt * x along the ray (the projector's ray sum before |D|).  With
@@ -163,9 +164,11 @@ __device__ __forceinline__ double ray_walk(const GeomDev &g, const T *__restrict
         const int bytes = (int)(sizeof(T) * (size_t)g.nx * g.ny * g.nz);
         const __amdgpu_buffer_rsrc_t xr =
             __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, bytes, BUF_WORD3);
-        ray_walk_visit<CONE, false>(g, ce, re, sx, sy, sz, [&](unsigned idx, double dt) {
-            acc = fma(dt, buf_load<T>(xr, idx), acc);
-        });
+        const int es = (int)sizeof(T);  // strides in bytes
+        ray_walk_visit<CONE, false>(g, ce, re, sx * es, sy * es, sz * es,
+                                    [&](unsigned off, double dt) {
+                                        acc = fma(dt, buf_load<T>(xr, off), acc);
+                                    });
     } else {
         ray_walk_visit<CONE, true>(g, ce, re, sx, sy, sz, [&](unsigned idx, double dt) {
             acc = fma(dt, (double)x[idx], acc);
