@@ -52,11 +52,11 @@ HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 # (profiles/cone256_kernels_hbm_traffic_pmc.md).
 MEASURED_TRAFFIC = [
     # project_kernel<float, cone, 2 columns, 4 waves> (z-fastest companion):
-    # 2139764.9 + 84167.8 KiB
+    # 2144600.7 + 82805.7 KiB
     {"kernel": "project", "stored": None, "tile": (2, 4),
      "sources": ["paper_1105_4002_amd/csrc/project.hip",
                  "paper_1105_4002_amd/csrc/raywalk.hpp"],
-     "sha256_prefix": "c4c7f6265be2cad6", "bytes": (2 * 2139764.9 + 84167.8) * 1024},
+     "sha256_prefix": "2e4814f4ed47c1aa", "bytes": (2 * 2144600.7 + 82805.7) * 1024},
     # backproject_sym_kernel<float, quarter turns, z mirror, 4 deep>: 52398.0 + 66402.7 KiB
     {"kernel": "backproject", "stored": False, "tile": None,
      "sources": ["paper_1105_4002_amd/csrc/backproject.hip",
