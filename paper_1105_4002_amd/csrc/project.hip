@@ -99,7 +99,8 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
             sx = g.ny;
             sy = 1;
         }
-        const double s = ray_walk<T, CONE, BUF>(g, xs, ce, re, sx, sy, sz);
+        const double s = ray_walk<T, CONE, BUF, sizeof(T) == 4 && column_tiles(WC)>(
+            g, xs, ce, re, sx, sy, sz);
         const double dn = CONE ? g.dnorm[(size_t)row * g.cols + col] : g.dnorm[v];
         const size_t i = ((size_t)v * g.rows + row) * g.cols + col;
         double ri = s * dn;

@@ -21,22 +21,64 @@ __device__ __forceinline__ void slab(double lo, double hi, double S, double invD
     }
 }
 
-// The walk itself.  Calls enter(ix, iy, iz, px, py, pz) once with the entry
-// voxel and the direction of travel along each axis (true: increasing
-// index), then, voxel by voxel, visit(dt) with dt >= 0 the parameter length
-// inside the current voxel (multiply by |D| for the length; dt may be 0 where
-// two crossings coincide) followed, unless the ray has left the volume, by
-// move(ax, ay, az): which axes' planes the ray crosses into the next voxel.
-// The next crossing of each axis is plane_t(X) of the next plane X, the
-// segment ends at the nearest one, and every axis whose crossing is reached
-// advances (a tie of two axes is one crossing, so no zero-length piece is
-// visited).  The exit crossing of each axis is computed with the same formula
-// as the slab exit, so no voxel outside the volume is reached before t
-// reaches tmax.
-template <bool CONE, class Enter, class Visit, class Move>
-__device__ __forceinline__ void ray_walk_core(const GeomDev &g, const ColEntry &ce,
-                                              const RowEntry &re, Enter &&enter, Visit &&visit,
-                                              Move &&move)
+// One step of the walk: the segment from t to the nearest crossing (its
+// parameter length is returned; inside: the ray is still in the volume after
+// it), then the move across that crossing into the next voxel.
+__device__ __forceinline__ double walk_step(double &t, double tmax, double &Xn, double &Yn,
+                                            double &Zn, double &tnx, double &tny, double &tnz,
+                                            int &idx, int stx, int sty, int stz, int hx, int hy,
+                                            int hz, double ivx, double ivy, double ivz, double ox,
+                                            double oy, double oz, bool &inside)
+{
+    const double tn = fmin(fmin(tnx, tny), fmin(tnz, tmax));
+    const double dt = tn - t;
+    t = tn;
+    inside = t < tmax;
+    // inside: tn is one of the three crossings, and if neither x's nor y's,
+    // then z's
+    const bool ax = tnx <= tn, ay = tny <= tn;
+    const bool axy = ax || ay, my = ay && !ax;
+    idx += ax ? stx : (ay ? sty : stz);
+    // the moving axis steps to its next plane and the others add 0; all
+    // three crossings are then recomputed, an unmoved plane giving its
+    // previous crossing again bit for bit
+    Xn += __hiloint2double(ax ? hx : 0, 0);
+    Yn += __hiloint2double(my ? hy : 0, 0);
+    Zn += __hiloint2double(axy ? 0 : hz, 0);
+    tnx = plane_t(Xn, ivx, ox);
+    tny = plane_t(Yn, ivy, oy);
+    tnz = plane_t(Zn, ivz, oz);
+    return dt;
+}
+
+// The walk itself: the sum over the ray's voxels, in order, of dt times the
+// voxel's value fetch(index), with dt >= 0 the parameter length inside the
+// voxel (multiply by |D| for the length; dt may be 0, see below).  The
+// volume is read through strides (sx, sy, sz), so that a copy stored in
+// another axis order can serve rays whose neighbours then touch adjacent
+// addresses; CLAMP clamps each fetched index to the volume as well (for
+// loads without a hardware range check; with one, an index off the volume
+// reads 0).  The next crossing of each axis is plane_t(X) of the next plane
+// X and the segment ends at the nearest one.  One plane is crossed per step:
+// where two or three crossings coincide (the ray passes through an edge or a
+// corner) the first reached axis in the order x, y, z moves and the next
+// step, in the voxel beside the edge, has length 0 -- a zero entry of A,
+// which adds nothing to the sum.  The exit crossing of each axis is computed
+// with the same formula as the slab exit, so no voxel outside the volume is
+// reached before t reaches tmax.
+//
+// With AHEAD, each step fetches the next voxel's value before it adds the
+// current one (the addresses do not depend on the data), so a load has a
+// whole step to arrive.  The lanes of a wave then step together until the
+// last of their rays has left the volume (a wave-uniform loop, no per-lane
+// exit): after its exit crossing a ray's steps have length 0 (every crossing
+// is then at or past tmax), and what they fetch, off the volume or not, adds
+// nothing.  Without AHEAD a step fetches its own voxel and a lane leaves the
+// loop at its exit.  Both add the same terms in the same order.
+template <bool CONE, bool CLAMP, bool AHEAD, class Fetch>
+__device__ __forceinline__ double ray_walk_sum(const GeomDev &g, const ColEntry &ce,
+                                               const RowEntry &re, int sx, int sy, int sz,
+                                               Fetch &&fetch)
 {
     const double lox = -g.hx, loy = -g.hy, loz = -g.hz;
     double tmin = CONE ? 0.0 : -INFINITY;
@@ -46,7 +88,7 @@ __device__ __forceinline__ void ray_walk_core(const GeomDev &g, const ColEntry &
     slab(loy, g.hy, ce.Sy, ce.invDy, ce.oy, tmin, tmax, hit);
     slab(loz, g.hz, re.Sz, re.invDz, re.oz, tmin, tmax, hit);
     if (!hit || !(tmax > tmin))
-        return;
+        return 0.0;
 
     // entry voxel (an axis the ray runs parallel to keeps its coordinate;
     // the clamp absorbs rounding at the entry face)
@@ -57,8 +99,11 @@ __device__ __forceinline__ void ray_walk_core(const GeomDev &g, const ColEntry &
     iy = min(max(iy, 0), g.ny - 1);
     iz = min(max(iz, 0), g.nz - 1);
 
+    // directions of travel (true: increasing index) and the index steps
     const bool px = ce.Dx > 0.0, py = ce.Dy > 0.0, pz = re.Dz > 0.0;
-    enter(ix, iy, iz, px, py, pz);
+    const int stx = px ? sx : -sx, sty = py ? sy : -sy, stz = pz ? sz : -sz;
+    const unsigned last = (unsigned)(g.nx * g.ny * g.nz - 1);
+    int idx = ix * sx + iy * sy + iz * sz;
     // An axis the ray runs parallel to gets the crossing offset +inf:
     // fma(X, 0, +inf) = +inf, so its crossing is never reached.
     const double ox = ce.invDx != 0.0 ? ce.ox : INFINITY;
@@ -80,52 +125,46 @@ __device__ __forceinline__ void ray_walk_core(const GeomDev &g, const ColEntry &
     // lengths are >= 0; the first crossing may round to before tmin, and
     // starting t at the smaller of the two gives that segment length 0.
     double t = fmin(tmin, fmin(fmin(tnx, tny), fmin(tnz, tmax)));
-    const int cap = g.nx + g.ny + g.nz + 2;  // hard bound on the number of voxels
-    for (int it = 0; it < cap; ++it) {
-        const double tn = fmin(fmin(tnx, tny), fmin(tnz, tmax));
-        visit(tn - t);
-        t = tn;
-        if (!(t < tmax))
-            break;
-        const bool ax = tnx <= tn, ay = tny <= tn, az = tnz <= tn;
-        move(ax, ay, az);
-        // every reached axis moves to its next plane and the others add 0;
-        // all three crossings are then recomputed, an unmoved plane giving
-        // its previous crossing again bit for bit
-        Xn += __hiloint2double(ax ? hx : 0, 0);
-        Yn += __hiloint2double(ay ? hy : 0, 0);
-        Zn += __hiloint2double(az ? hz : 0, 0);
-        tnx = plane_t(Xn, ce.invDx, ox);
-        tny = plane_t(Yn, ce.invDy, oy);
-        tnz = plane_t(Zn, re.invDz, oz);
+    // hard bound on the steps: each moves one plane, at most n - 1 per axis
+    // before the exit crossing
+    const int cap = g.nx + g.ny + g.nz + 2;
+    const auto at = [&](int i) { return CLAMP ? min((unsigned)i, last) : (unsigned)i; };
+    double acc = 0.0;
+    if (AHEAD) {
+        // two steps per iteration, the fetched values alternating between
+        // xa and xb; the wave leaves once none of its rays is still inside
+        // after the second (a ray that left at the first adds a step of
+        // length 0)
+        double xa = fetch(at(idx)), xb;
+        for (int it = 0; it < cap; it += 2) {
+            bool inside;
+            const double d1 = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty, stz,
+                                        hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox, oy, oz,
+                                        inside);
+            xb = fetch(at(idx));
+            acc = fma(d1, xa, acc);
+            const double d2 = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty, stz,
+                                        hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox, oy, oz,
+                                        inside);
+            xa = fetch(at(idx));
+            acc = fma(d2, xb, acc);
+            if (!__any(inside))
+                break;
+        }
+    } else {
+#pragma unroll 2
+        for (int it = 0; it < cap; ++it) {
+            const unsigned cur = at(idx);
+            bool inside;
+            const double dt = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty, stz,
+                                        hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox, oy, oz,
+                                        inside);
+            acc = fma(dt, fetch(cur), acc);
+            if (!inside)
+                break;
+        }
     }
-}
-
-// Visits the ray's voxels in order, calling visit(index, dt) (the walk of
-// ray_walk_core with the voxel's index into the volume).  The volume is read
-// through strides (sx, sy, sz), so that a copy stored in another axis order
-// can serve rays whose neighbours then touch adjacent addresses.  CLAMP
-// clamps each visited index to the volume as well (for loads without a
-// hardware range check).
-template <bool CONE, bool CLAMP, class Visit>
-__device__ __forceinline__ void ray_walk_visit(const GeomDev &g, const ColEntry &ce,
-                                               const RowEntry &re, int sx, int sy, int sz,
-                                               Visit &&visit)
-{
-    const unsigned last = (unsigned)(g.nx * g.ny * g.nz - 1);
-    int idx = 0, stx = 0, sty = 0, stz = 0;
-    ray_walk_core<CONE>(
-        g, ce, re,
-        [&](int ix, int iy, int iz, bool px, bool py, bool pz) {
-            stx = px ? sx : -sx;
-            sty = py ? sy : -sy;
-            stz = pz ? sz : -sz;
-            idx = ix * sx + iy * sy + iz * sz;
-        },
-        [&](double dt) { visit(CLAMP ? min((unsigned)idx, last) : (unsigned)idx, dt); },
-        [&](bool ax, bool ay, bool az) {
-            idx += (ax ? stx : 0) + (ay ? sty : 0) + (az ? stz : 0);
-        });
+    return acc;
 }
 
 // Loads of x[idx] through a buffer resource: the hardware checks each offset
@@ -153,28 +192,28 @@ __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uns
 // Sum of dt * x along the ray (the projector's ray sum before |D|).  With
 // BUF (volumes under 2^31 bytes: a buffer offset is a signed 32-bit number)
 // x is read through a range-checked buffer resource, otherwise through
-// clamped global loads; both read the same values.
-template <typename T, bool CONE, bool BUF>
+// clamped global loads; both read the same values.  AHEAD selects the walk
+// with its loads a step ahead (see ray_walk_sum).  It pays where a wave's
+// rays have nearly equal lengths (the column ray tiles) in single
+// precision; where they do not (row tiles), or for double (twice the bytes
+// per fetch), the lanes that step on past their exit cost more than the
+// early loads save.
+template <typename T, bool CONE, bool BUF, bool AHEAD>
 __device__ __forceinline__ double ray_walk(const GeomDev &g, const T *__restrict__ x,
                                            const ColEntry &ce, const RowEntry &re, int sx,
                                            int sy, int sz)
 {
-    double acc = 0.0;
     if (BUF) {
         const int bytes = (int)(sizeof(T) * (size_t)g.nx * g.ny * g.nz);
         const __amdgpu_buffer_rsrc_t xr =
             __builtin_amdgcn_make_buffer_rsrc((void *)x, (short)0, bytes, BUF_WORD3);
         const int es = (int)sizeof(T);  // strides in bytes
-        ray_walk_visit<CONE, false>(g, ce, re, sx * es, sy * es, sz * es,
-                                    [&](unsigned off, double dt) {
-                                        acc = fma(dt, buf_load<T>(xr, off), acc);
-                                    });
-    } else {
-        ray_walk_visit<CONE, true>(g, ce, re, sx, sy, sz, [&](unsigned idx, double dt) {
-            acc = fma(dt, (double)x[idx], acc);
-        });
+        return ray_walk_sum<CONE, false, AHEAD>(
+            g, ce, re, sx * es, sy * es, sz * es,
+            [&](unsigned off) { return buf_load<T>(xr, off); });
     }
-    return acc;
+    return ray_walk_sum<CONE, true, AHEAD>(
+        g, ce, re, sx, sy, sz, [&](unsigned idx) { return (double)x[idx]; });
 }
 
 // whether a volume of this geometry fits the buffer path

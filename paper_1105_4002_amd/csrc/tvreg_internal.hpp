@@ -127,7 +127,7 @@ inline int default_tile_cols(int rows) { return rows % 32 == 0 ? 2 : 64; }
 // tiles (1 or 2 detector columns per wave) read a z-fastest copy
 // [y][x][z]; row tiles (8 or more columns) read the y-fastest copy [z][x][y]
 // for the views whose rays run mostly along x.
-__host__ __device__ inline bool column_tiles(int pj_wc) { return pj_wc <= 2; }
+__host__ __device__ constexpr bool column_tiles(int pj_wc) { return pj_wc <= 2; }
 
 // The feasible set Q = [lo, hi]^N (lo = 0, hi = +inf: the nonnegative
 // orthant) and its projection, a clip evaluated in double.
