@@ -292,10 +292,13 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
 // each image's detector tile -- the rotated views, the mirrored rows --
 // from LDS (r |D| in double, as the plain gather stages it).  Each image
 // sums its views in the order v + q V / ROT, v = 0 .. V - 1 (the identity
-// image: the plain gather's order and values).
+// image: the plain gather's order and values, wherever a view's footprint
+// fits one tile; a larger one is gathered in tiles, its rows in a different
+// order).
 constexpr int STILE_R = 16;  // detector rows the symmetric gather stages per view
-constexpr int STILE_C = 48;  // ... and columns
+constexpr int STILE_C = 44;  // ... and columns
 constexpr int STILE_S = STILE_C + 1;  // odd row stride (in doubles)
+constexpr double FLAT_IDZ = 1e300;    // stands for 1/Dz = infinity (|Z| FLAT_IDZ stays finite)
 
 template <int NI>
 struct SymTile {
@@ -304,38 +307,20 @@ struct SymTile {
     double iDz[STILE_R + 1];
 };
 
-// Global-memory source of one image for views whose footprint exceeds the
-// tile: the cell's ray entries of view v, image data of view vq with rows
-// mirrored when MIRROR.
-template <typename T, bool MIRROR>
-struct SymGlobalSrc {
-    const GeomDev *g;
-    const ColEntry *colv;  // view v's column entries
-    const T *rq;           // view vq's data
-    __device__ ColEntry column(int c) const { return colv[c]; }
-    __device__ double Sz(int r) const { return g->row[r].Sz; }
-    __device__ double invDz(int r) const { return g->row[r].invDz; }
-    __device__ double oz_(int r) const { return g->row[r].oz; }
-    __device__ double value(int r, int c) const
-    {
-        const int rm = MIRROR ? g->rows - 1 - r : r;
-        return (double)rq[(size_t)rm * g->cols + c] * g->dnorm[(size_t)r * g->cols + c];
-    }
-};
-
-template <bool FLAT, int NI, int CZ>
+// One detector row of one column for voxel layer k: the ray's length in
+// the voxel (its xy interval [tl, th] clipped by the layer's crossings
+// Z / Dz; the flat row's huge 1/Dz gives th - tl or 0) applied to the NI
+// images.  A row past the footprint (ok false) reads the zero row.
+template <int NI, int CZ>
 __device__ __forceinline__ void sym_row(const SymTile<NI> &S, int rel, int cc, double Z0,
-                                        double Z1, double tl, double th, double flat_len, bool ok,
+                                        double Z1, double tl, double th, bool ok,
                                         double (&acc)[NI][CZ], int k)
 {
     const int o = (ok ? rel : STILE_R) * STILE_S + cc;
     const double idz = S.iDz[ok ? rel : STILE_R];
     const double t0 = Z0 * idz, t1 = Z1 * idz;
     const double lo = fmax(tl, fmin(t0, t1)), hi = fmin(th, fmax(t0, t1));
-    double len = hi - lo;
-    if (FLAT)
-        len = idz != 0.0 ? len : flat_len;
-    len = fmax(len, 0.0);
+    const double len = fmax(hi - lo, 0.0);
 #pragma unroll
     for (int i = 0; i < NI; ++i)
         acc[i][k] = fma(len, S.rt[i][o], acc[i][k]);
@@ -343,7 +328,7 @@ __device__ __forceinline__ void sym_row(const SymTile<NI> &S, int rel, int cc, d
 
 // The cone-beam gather of gather_cone_tile for the cell's voxels iz0 ..
 // iz0 + CZ - 1 below mz, every ray applied to the NI images.
-template <int CZ, bool FLAT, int NI>
+template <int CZ, int NI>
 __device__ __forceinline__ void gather_cone_sym(const GeomDev &g, const SymTile<NI> &S,
                                                 double c, double s, double X0, double X1,
                                                 double Y0, double Y1, int iz0, int mz, int C0,
@@ -372,11 +357,10 @@ __device__ __forceinline__ void gather_cone_sym(const GeomDev &g, const SymTile<
             if (iz0 + k < mz) {  // block-uniform
                 const int lo = (int)fmax(ceil(fmin(qa, qb) + row_lo_off), 0.0);
                 const int hi = (int)fmin(floor(fmax(pa, pb) + row_hi_off), row_last);
-                const double fl = FLAT && Z0 <= 0.0 && 0.0 < Z1 ? th - tl : 0.0;
-                sym_row<FLAT>(S, lo, cc, Z0, Z1, tl, th, fl, lo <= hi, acc, k);
-                sym_row<FLAT>(S, lo + 1, cc, Z0, Z1, tl, th, fl, lo + 1 <= hi, acc, k);
+                sym_row(S, lo, cc, Z0, Z1, tl, th, lo <= hi, acc, k);
+                sym_row(S, lo + 1, cc, Z0, Z1, tl, th, lo + 1 <= hi, acc, k);
                 for (int rel = lo + 2; rel <= hi; ++rel)  // wide footprints only
-                    sym_row<FLAT>(S, rel, cc, Z0, Z1, tl, th, fl, true, acc, k);
+                    sym_row(S, rel, cc, Z0, Z1, tl, th, true, acc, k);
             }
             Z0 = Z1;
             qa = pa;
@@ -433,74 +417,75 @@ __device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T 
     if (tid == 0)
         S.iDz[STILE_R] = 1.0;
 
-    for (int v = 0; v < g.nviews; ++v) {
+    // detector columns C0..C1 and rows R0..R1 the block's voxels project to
+    // in view v (empty when C1 < C0 or R1 < R0)
+    const auto footprint = [&](int v, int &C0, int &C1, int &R0, int &R1) {
         const double c = g.cs[v].x, s = g.cs[v].y;
         double f0, f1, bmin, bmax;
         u_footprint<true>(g, c, s, bX0, bX1, bY0, bY1, f0, f1, bmin, bmax);
-        int C0, C1, R0, R1;
         index_range(f0, f1, 0, g.cols - 1, C0, C1);
         const double i0 = g.SDD * rcp(g.R - bmin), i1 = g.SDD * rcp(g.R - bmax);
         const double wlo = fmin(bZ0 * i0, bZ0 * i1), whi = fmax(bZ1 * i0, bZ1 * i1);
         index_range(wlo * g.ipv + g.rv0, whi * g.ipv + g.rv0, 0, g.rows - 1, R0, R1);
-        const int nc = C1 - C0 + 1, nr = R1 - R0 + 1;
-        if (nc <= 0 || nr <= 0)
-            continue;  // block-uniform
-        if (nc <= STILE_C && nr <= STILE_R) {
-            for (int i = tid; i < nr * nc; i += BP_THREADS) {
-                const int rr = i / nc, cc = i - rr * nc;
-                const int row = R0 + rr, col = C0 + cc;
-                const int o = rr * STILE_S + cc;
-                // |D| of a mirrored row is that of the row (rows symmetric about w = 0)
-                const double dn = g.dnorm[(size_t)row * g.cols + col];
-                int vq = v;
-#pragma unroll
-                for (int q = 0; q < ROT; ++q) {
-                    const T *rq = r + (size_t)vq * view_stride;
-                    S.rt[q * NM][o] = (double)rq[(size_t)row * g.cols + col] * dn;
-                    if (MIR)
-                        S.rt[q * NM + 1][o] =
-                            (double)rq[(size_t)(g.rows - 1 - row) * g.cols + col] * dn;
-                    vq += vstep;
-                    vq -= vq >= g.nviews ? g.nviews : 0;
-                }
-            }
-            for (int i = tid; i < nc; i += BP_THREADS) {
-                const ColEntry e = g.col[(size_t)v * g.cols + C0 + i];
-                S.Sx[i] = e.Sx;
-                S.Sy[i] = e.Sy;
-                S.iDx[i] = e.invDx;
-                S.iDy[i] = e.invDy;
-                S.ox[i] = e.ox;
-                S.oy[i] = e.oy;
-            }
-            for (int i = tid; i < nr; i += BP_THREADS)
-                S.iDz[i] = g.row[R0 + i].invDz;
-            __syncthreads();
-            if (active) {
-                if (g.flat_row >= R0 && g.flat_row <= R1)  // block-uniform
-                    gather_cone_sym<CZ, true>(g, S, c, s, X0, X1, Y0, Y1, iz0, mz, C0, C1, R0,
-                                              R1, acc);
-                else
-                    gather_cone_sym<CZ, false>(g, S, c, s, X0, X1, Y0, Y1, iz0, mz, C0, C1, R0,
-                                               R1, acc);
-            }
-            __syncthreads();
-        } else if (active) {  // the generic arithmetic, image by image
-            const ColEntry *colv = g.col + (size_t)v * g.cols;
+    };
+    // view v's NI detector tiles (r |D| in double) and its column and row
+    // entries into LDS
+    const auto stage = [&](int v, int C0, int R0, int nc, int nr) {
+        for (int i = tid; i < nr * nc; i += BP_THREADS) {
+            const int rr = i / nc, cc = i - rr * nc;
+            const int row = R0 + rr, col = C0 + cc;
+            const int o = rr * STILE_S + cc;
+            // |D| of a mirrored row is that of the row (rows symmetric about w = 0)
+            const double dn = g.dnorm[(size_t)row * g.cols + col];
             int vq = v;
 #pragma unroll
             for (int q = 0; q < ROT; ++q) {
                 const T *rq = r + (size_t)vq * view_stride;
-                const SymGlobalSrc<T, false> src{&g, colv, rq};
-                gather_view<true, CZ>(g, src, c, s, X0, X1, Y0, Y1, iz0, 0, g.cols - 1, 0,
-                                      g.rows - 1, acc[q * NM]);
-                if (MIR) {
-                    const SymGlobalSrc<T, true> srm{&g, colv, rq};
-                    gather_view<true, CZ>(g, srm, c, s, X0, X1, Y0, Y1, iz0, 0, g.cols - 1, 0,
-                                          g.rows - 1, acc[q * NM + NM - 1]);
-                }
+                S.rt[q * NM][o] = (double)rq[(size_t)row * g.cols + col] * dn;
+                if (MIR)
+                    S.rt[q * NM + 1][o] = (double)rq[(size_t)(g.rows - 1 - row) * g.cols + col] * dn;
                 vq += vstep;
                 vq -= vq >= g.nviews ? g.nviews : 0;
+            }
+        }
+        for (int i = tid; i < nc; i += BP_THREADS) {
+            const ColEntry e = g.col[(size_t)v * g.cols + C0 + i];
+            S.Sx[i] = e.Sx;
+            S.Sy[i] = e.Sy;
+            S.iDx[i] = e.invDx;
+            S.iDy[i] = e.invDy;
+            S.ox[i] = e.ox;
+            S.oy[i] = e.oy;
+        }
+        // The flat row (invDz = 0: its rays run in the plane w = 0) gets a
+        // huge finite 1/Dz instead: its crossing parameters Z0 / Dz, Z1 / Dz
+        // are then -huge, 0 or +huge, and the clip of sym_row leaves the
+        // whole xy interval th - tl exactly when Z0 <= 0 < Z1 and nothing
+        // otherwise -- the flat row's length, with no separate path.
+        for (int i = tid; i < nr; i += BP_THREADS) {
+            const double idz = g.row[R0 + i].invDz;
+            S.iDz[i] = idz != 0.0 ? idz : FLAT_IDZ;
+        }
+    };
+
+    // One path per view: its footprint in LDS tiles (one tile when it fits,
+    // as on the usual scans; else column-major chunks of STILE_C columns by
+    // STILE_R rows), each staged and gathered from LDS.  (A second, generic
+    // path in the loop would keep the accumulators in other registers on each
+    // path and pay moves between them per view.)
+    for (int v = 0; v < g.nviews; ++v) {
+        int C0, C1, R0, R1;
+        footprint(v, C0, C1, R0, R1);
+        for (int cb = C0; cb <= C1; cb += STILE_C) {  // block-uniform
+            const int ce = min(cb + STILE_C - 1, C1), nc = ce - cb + 1;
+            for (int rb = R0; rb <= R1; rb += STILE_R) {
+                const int re = min(rb + STILE_R - 1, R1), nr = re - rb + 1;
+                stage(v, cb, rb, nc, nr);
+                __syncthreads();
+                if (active)
+                    gather_cone_sym<CZ>(g, S, g.cs[v].x, g.cs[v].y, X0, X1, Y0, Y1, iz0, mz, cb,
+                                        ce, rb, re, acc);
+                __syncthreads();
             }
         }
     }
