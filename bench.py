@@ -677,20 +677,26 @@ def main() -> int:
     torch.cuda.synchronize()
 
     log(f"timed: {args.steps} UPN iterations")
-    tv.profile_reset()
-    tv.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     xk, ik, _ = tv.solve(G32, b32, method=tv.UPN, eps=0.0, max_iter=args.steps, x0=xw,
                          L_bar=iw["L"], workspace=ws32, **common)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tv.profile_enable(False)
-    stats = tv.profile_stats()
     elapsed = t1 - t0
     value = ik["grad_evals"] / elapsed
     log(f"timed solve: {elapsed:.3f} s, {ik['grad_evals']} gradient evaluations, "
         f"{ik['func_evals']} trial evaluations")
+    # per-kernel times: the same iterations again with the library's HIP-event
+    # timing of each launch on (not part of the timed solve above: its events
+    # and their readout between the line-search trials add host time per step)
+    tv.profile_reset()
+    tv.profile_enable(True)
+    tv.solve(G32, b32, method=tv.UPN, eps=0.0, max_iter=args.steps, x0=xw, L_bar=iw["L"],
+             workspace=ws32, **common)
+    torch.cuda.synchronize()
+    tv.profile_enable(False)
+    stats = tv.profile_stats()
 
     kernels = {}
     for name, (cnt, ms) in stats.items():

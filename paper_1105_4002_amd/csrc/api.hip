@@ -578,7 +578,7 @@ extern "C" tvreg_status tvreg_tv_hessvec(int32_t nx, int32_t ny, int32_t nz,
 namespace {
 
 struct Layout {
-    size_t vecN[6], vecM[3], partials, scalars, total;  // vecN[5]: transposed copy
+    size_t vecN[6], vecM[3], partials, total;  // vecN[5]: transposed copy
 };
 
 Layout solve_layout(const tvreg_geometry *G)
@@ -596,8 +596,6 @@ Layout solve_layout(const tvreg_geometry *G)
     }
     L.partials = off;
     off = align_up(off + partial_bytes(G->pstride), 256);
-    L.scalars = off;
-    off = align_up(off + sizeof(double) * 2 * S_COUNT, 256);
     L.total = off;
     return L;
 }
@@ -617,8 +615,7 @@ struct Runner {
     hipStream_t st;
     double *part;
     int pstride;
-    double *dsc;        // device scalars [S_COUNT]
-    HostScalars hs;     // host copy
+    HostScalars hs;     // the slots' sums, written by the finaliser straight to host memory
     SlotList pend;
     bool prof = false;
     struct Ev {
@@ -687,14 +684,15 @@ struct Runner {
             }
         pend.slot[pend.n] = slot;
         pend.count[pend.n] = count;
-        pend.dst[pend.n] = dsc + slot;
+        pend.dst[pend.n] = hs.p + slot;
         pend.n++;
     }
     tvreg_status read()
     {
+        // the finaliser writes the pending sums into the page-locked host
+        // slots (no separate copy); they are read once the stream is done
         TVR_HIP(launch_finalize(pend, part, pstride, st));
         pend.n = 0;
-        TVR_HIP(hipMemcpyAsync(hs.p, dsc, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
         TVR_HIP(spin_sync(st, hs.done));
         resolve();
         return TVREG_OK;
@@ -1099,7 +1097,6 @@ static tvreg_status solve_impl(const tvreg_geometry *G, const T *b, const tvreg_
     s.run.st = st;
     s.run.part = (double *)(ws + L.partials);
     s.run.pstride = G->pstride;
-    s.run.dsc = (double *)(ws + L.scalars);
     s.run.pend.n = 0;
     if (!s.run.hs.p)
         return fail(TVREG_ENOMEM, "page-locked host buffer of %d doubles", (int)S_COUNT);
@@ -1107,7 +1104,7 @@ static tvreg_status solve_impl(const tvreg_geometry *G, const T *b, const tvreg_
         std::lock_guard<std::mutex> lk(g_prof.mu);
         s.run.prof = g_prof.on;
     }
-    TVR_HIP(hipMemsetAsync(s.run.dsc, 0, sizeof(double) * S_COUNT, st));
+    std::fill(s.run.hs.p, s.run.hs.p + S_COUNT, 0.0);
     const tvreg_status r = p->method == TVREG_GPBB ? s.gpbb(x, info) : s.gp_upn(x, info);
     if (s.run.prof && hipStreamSynchronize(st) == hipSuccess)
         s.run.resolve();

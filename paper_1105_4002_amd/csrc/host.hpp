@@ -93,10 +93,10 @@ inline hipError_t spin_sync(hipStream_t st, hipEvent_t ev)
     return e;
 }
 
-// Page-locked host copy of the scalar sums a solver reads back after each
-// line-search trial (a copy into pageable memory is staged and costs far more
-// than the copy itself), with the event its reads wait on.  p is null when
-// the allocation failed.
+// Page-locked host slots of the scalar sums a solver reads after each
+// line-search trial: the finaliser kernel writes them there directly (the
+// memory is mapped for the device), and the host reads them once the event
+// its reads wait on has completed.  p is null when the allocation failed.
 struct HostScalars {
     double *p = nullptr;
     hipEvent_t done = nullptr;  // polled by spin_sync after each read
