@@ -131,23 +131,25 @@ __device__ __forceinline__ double ray_walk_sum(const GeomDev &g, const ColEntry 
     const auto at = [&](int i) { return CLAMP ? min((unsigned)i, last) : (unsigned)i; };
     double acc = 0.0;
     if (AHEAD) {
-        // two steps per iteration, the fetched values alternating between
+        // four steps per iteration, the fetched values alternating between
         // xa and xb; the wave leaves once none of its rays is still inside
-        // after the second (a ray that left at the first adds a step of
-        // length 0)
+        // after the fourth (a ray that left earlier adds steps of length 0)
         double xa = fetch(at(idx)), xb;
-        for (int it = 0; it < cap; it += 2) {
+        for (int it = 0; it < cap; it += 4) {
             bool inside;
-            const double d1 = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty, stz,
-                                        hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox, oy, oz,
-                                        inside);
-            xb = fetch(at(idx));
-            acc = fma(d1, xa, acc);
-            const double d2 = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty, stz,
-                                        hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox, oy, oz,
-                                        inside);
-            xa = fetch(at(idx));
-            acc = fma(d2, xb, acc);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double d1 = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty,
+                                            stz, hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox,
+                                            oy, oz, inside);
+                xb = fetch(at(idx));
+                acc = fma(d1, xa, acc);
+                const double d2 = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty,
+                                            stz, hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox,
+                                            oy, oz, inside);
+                xa = fetch(at(idx));
+                acc = fma(d2, xb, acc);
+            }
             if (!__any(inside))
                 break;
         }
