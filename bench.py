@@ -96,13 +96,13 @@ FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed 
 # vector instruction issue: 256 CUs x 4 SIMDs x 16 lanes per clock at 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s
 # vector instructions per voxel step of the projector's walk loop (count of the
-# gfx950 code the build emits for the single-precision project_kernel on
-# volumes under 2 GiB: 47 per iteration of two steps, for the 2 x 32 column
-# tile's walk with its loads a step ahead as for the 64 x 1 row tile's.  Per step: 3 min for the segment end, the length,
-# 3 compares, 2 selects and 1 add for the byte offset, 4 selects, 3 adds and
-# 3 FMAs for the planes and next crossings, convert and accumulate; per
-# iteration: the exit compare, 2 for the iteration bound and 1 move)
-PROJECT_VALU_PER_STEP = 23.5
+# gfx950 code the build emits for the single-precision project_kernel of the
+# column ray tiles on volumes under 2 GiB: 89 per iteration of four steps.
+# Per step: 3 min for the segment end, the length, the compares and selects
+# that pick the moving axis and its byte-offset step, 3 adds and 3 FMAs for
+# the planes and next crossings, convert and accumulate; per iteration: the
+# exit test and the iteration bound.  The row tiles' walk takes 47 per two.)
+PROJECT_VALU_PER_STEP = 22.25
 
 
 def log(msg: str) -> None:
