@@ -52,16 +52,16 @@ HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 # (profiles/cone256_kernels_hbm_traffic_pmc.md).
 MEASURED_TRAFFIC = [
     # project_kernel<float, cone, 2 columns, 4 waves> (z-fastest companion):
-    # 2144600.7 + 82805.7 KiB
+    # 2444822.0 + 107994.3 KiB
     {"kernel": "project", "stored": None, "tile": (2, 4),
      "sources": ["paper_1105_4002_amd/csrc/project.hip",
                  "paper_1105_4002_amd/csrc/raywalk.hpp"],
-     "sha256_prefix": "2e4814f4ed47c1aa", "bytes": (2 * 2144600.7 + 82805.7) * 1024},
-    # backproject_sym_kernel<float, quarter turns, z mirror, 4 deep>: 52398.0 + 66402.7 KiB
+     "sha256_prefix": "8c9fac026a898787", "bytes": (2 * 2444822.0 + 107994.3) * 1024},
+    # backproject_sym_kernel<float, quarter turns, z mirror, 4 deep>: 48597.0 + 66352.0 KiB
     {"kernel": "backproject", "stored": False, "tile": None,
      "sources": ["paper_1105_4002_amd/csrc/backproject.hip",
                  "paper_1105_4002_amd/csrc/gather.hpp"],
-     "sha256_prefix": "28a3693bfe55cd68", "bytes": (2 * 52398.0 + 66402.7) * 1024},
+     "sha256_prefix": "ca48f9dc58088369", "bytes": (2 * 48597.0 + 66352.0) * 1024},
     # spmv_sym_kernel<float, quarter turns, z mirror>: 814996.4 + 77781.3 KiB
     {"kernel": "backproject", "stored": True, "tile": None,
      "sources": ["paper_1105_4002_amd/csrc/matrix.hip"], "sha256_prefix": "80160ee1be1d8553",
