@@ -18,8 +18,8 @@
 // only LDS.  The cone-beam inner loop is branch free: the two candidate rows
 // of each layer get the exact interval arithmetic, a row outside the range
 // reads the tile's zero row, and a non-positive length adds nothing.
-// A view whose footprint exceeds the tile (unusual geometries) takes the
-// generic arithmetic with global loads.
+// A cone-beam view whose footprint exceeds the tile is gathered tile by
+// tile; a parallel-beam one takes the generic arithmetic with global loads.
 #include "gather.hpp"
 #include "ray3d.hpp"
 #include "reduce.hpp"
@@ -35,6 +35,12 @@ constexpr int BP_THREADS = BP_TX * BP_TY;
 constexpr int TILE_C = 48;  // detector columns a block stages per view
 constexpr int TILE_R = 32;  // detector rows a block stages per view
 constexpr int TILE_S = TILE_C + 1;  // odd row stride (in doubles) against bank conflicts
+// A flat detector row (invDz = 0: its rays run in the plane w = 0) is staged
+// with this huge finite 1/Dz: its crossing parameters Z0 / Dz, Z1 / Dz are
+// then -huge, 0 or +huge (|Z| FLAT_IDZ stays finite), and the interval clip
+// leaves the whole xy interval th - tl exactly when Z0 <= 0 < Z1 and nothing
+// otherwise -- the flat row's length, with no separate path.
+constexpr double FLAT_IDZ = 1e300;
 
 // The block's LDS copy of one view.  Row TILE_R of rt and iDz is a zero row
 // (value 0, slope 1) that the cone gather reads for candidate rows outside
@@ -69,28 +75,22 @@ struct TileSrc {
 };
 
 // Cone-beam gather of one view from the block's tile.  The source sits at
-// z = 0 (Sz = 0, so the plane parameter is Z * invDz).  A row with w = 0 runs
-// in the plane z = 0 and belongs to the layer containing 0; FLAT compiles
-// that case in (only a view whose rows include it needs it).  A candidate
-// row outside the voxel's range (ok false) reads the tile's zero row.  The
-// interval length is clamped at 0 and weights the value in one fma.
-template <bool FLAT>
+// z = 0 (Sz = 0, so the plane parameter is Z * invDz; a flat row carries
+// FLAT_IDZ).  A candidate row outside the voxel's range (ok false) reads the
+// tile's zero row.  The interval length is clamped at 0 and weights the
+// value in one fma.
 __device__ __forceinline__ void cone_row(const Tile &T_, int rel, int cc, double Z0, double Z1,
-                                         double tl, double th, double flat_len, bool ok,
-                                         double &acc)
+                                         double tl, double th, bool ok, double &acc)
 {
     const int rr = ok ? rel : TILE_R;
     const double val = T_.rt[rr * TILE_S + cc];
     const double idz = T_.iDz[rr];
     const double t0 = Z0 * idz, t1 = Z1 * idz;
     const double lo = fmax(tl, fmin(t0, t1)), hi = fmin(th, fmax(t0, t1));
-    double len = hi - lo;
-    if (FLAT)
-        len = idz != 0.0 ? len : flat_len;
-    acc = fma(fmax(len, 0.0), val, acc);
+    acc = fma(fmax(hi - lo, 0.0), val, acc);
 }
 
-template <int CZ, bool FLAT>
+template <int CZ>
 __device__ __forceinline__ void gather_cone_tile(const GeomDev &g, const Tile &T_, double c,
                                                  double s, double X0, double X1, double Y0,
                                                  double Y1, int iz0, int C0, int C1, int R0,
@@ -124,11 +124,10 @@ __device__ __forceinline__ void gather_cone_tile(const GeomDev &g, const Tile &T
                 // candidate rows relative to the tile (empty when hi < lo)
                 const int lo = (int)fmax(ceil(fmin(qa, qb) + row_lo_off), 0.0);
                 const int hi = (int)fmin(floor(fmax(pa, pb) + row_hi_off), row_last);
-                const double fl = FLAT && Z0 <= 0.0 && 0.0 < Z1 ? th - tl : 0.0;
-                cone_row<FLAT>(T_, lo, cc, Z0, Z1, tl, th, fl, lo <= hi, acc[k]);
-                cone_row<FLAT>(T_, lo + 1, cc, Z0, Z1, tl, th, fl, lo + 1 <= hi, acc[k]);
+                cone_row(T_, lo, cc, Z0, Z1, tl, th, lo <= hi, acc[k]);
+                cone_row(T_, lo + 1, cc, Z0, Z1, tl, th, lo + 1 <= hi, acc[k]);
                 for (int rel = lo + 2; rel <= hi; ++rel)  // wide footprints only
-                    cone_row<FLAT>(T_, rel, cc, Z0, Z1, tl, th, fl, true, acc[k]);
+                    cone_row(T_, rel, cc, Z0, Z1, tl, th, true, acc[k]);
             }
             Z0 = Z1;
             qa = pa;
@@ -224,14 +223,15 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
             continue;  // block-uniform: nothing of this view reaches the block
         const T *rv = r + (size_t)v * view_stride;
         const double dnv = CONE ? 1.0 : g.dnorm[v];
-        if (nc <= TILE_C && nr <= TILE_R) {
-            for (int i = tid; i < nr * nc; i += BP_THREADS) {
-                const int rr = i / nc, cc = i - rr * nc;
-                const size_t p = (size_t)(R0 + rr) * g.cols + (C0 + cc);
+        // the view's detector rectangle rows rb..re x columns cb..ce into the tile
+        const auto stage = [&](int cb, int rb, int ncs, int nrs) {
+            for (int i = tid; i < nrs * ncs; i += BP_THREADS) {
+                const int rr = i / ncs, cc = i - rr * ncs;
+                const size_t p = (size_t)(rb + rr) * g.cols + (cb + cc);
                 tile.rt[rr * TILE_S + cc] = (double)rv[p] * (CONE ? g.dnorm[p] : dnv);
             }
-            for (int i = tid; i < nc; i += BP_THREADS) {
-                const ColEntry e = g.col[(size_t)v * g.cols + C0 + i];
+            for (int i = tid; i < ncs; i += BP_THREADS) {
+                const ColEntry e = g.col[(size_t)v * g.cols + cb + i];
                 tile.Sx[i] = e.Sx;
                 tile.Sy[i] = e.Sy;
                 tile.iDx[i] = e.invDx;
@@ -239,26 +239,38 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
                 tile.ox[i] = e.ox;
                 tile.oy[i] = e.oy;
             }
-            for (int i = tid; i < nr; i += BP_THREADS) {
-                const RowEntry e = g.row[R0 + i];
+            for (int i = tid; i < nrs; i += BP_THREADS) {
+                const RowEntry e = g.row[rb + i];
                 tile.Sz[i] = e.Sz;
-                tile.iDz[i] = e.invDz;
+                // cone: a flat row (invDz = 0) gets a huge finite 1/Dz, whose
+                // clip in cone_row gives its length (see FLAT_IDZ)
+                tile.iDz[i] = CONE && e.invDz == 0.0 ? FLAT_IDZ : e.invDz;
                 tile.oz[i] = e.oz;
             }
+        };
+        if (CONE) {
+            // One path per view: the footprint in tiles (one when it fits;
+            // else column-major chunks of TILE_C columns by TILE_R rows).  A
+            // second path in the loop would hold the accumulators in other
+            // registers on each and pay moves between them per view.
+            for (int cb = C0; cb <= C1; cb += TILE_C) {  // block-uniform
+                const int ce = min(cb + TILE_C - 1, C1);
+                for (int rb = R0; rb <= R1; rb += TILE_R) {
+                    const int re = min(rb + TILE_R - 1, R1);
+                    stage(cb, rb, ce - cb + 1, re - rb + 1);
+                    __syncthreads();
+                    if (active)
+                        gather_cone_tile<CZ>(g, tile, c, s, X0, X1, Y0, Y1, iz0, cb, ce, rb, re,
+                                             acc);
+                    __syncthreads();
+                }
+            }
+        } else if (nc <= TILE_C && nr <= TILE_R) {
+            stage(C0, R0, nc, nr);
             __syncthreads();
             if (active) {
-                if (CONE) {
-                    if (g.flat_row >= R0 && g.flat_row <= R1)  // block-uniform
-                        gather_cone_tile<CZ, true>(g, tile, c, s, X0, X1, Y0, Y1, iz0, C0, C1,
-                                                   R0, R1, acc);
-                    else
-                        gather_cone_tile<CZ, false>(g, tile, c, s, X0, X1, Y0, Y1, iz0, C0,
-                                                    C1, R0, R1, acc);
-                } else {
-                    const TileSrc src{&tile, C0, R0};
-                    gather_view<false, CZ>(g, src, c, s, X0, X1, Y0, Y1, iz0, C0, C1, R0, R1,
-                                           acc);
-                }
+                const TileSrc src{&tile, C0, R0};
+                gather_view<false, CZ>(g, src, c, s, X0, X1, Y0, Y1, iz0, C0, C1, R0, R1, acc);
             }
             __syncthreads();
         } else if (active) {
@@ -298,7 +310,6 @@ __device__ __forceinline__ void backproject_block(const GeomDev &g, const T *__r
 constexpr int STILE_R = 16;  // detector rows the symmetric gather stages per view
 constexpr int STILE_C = 44;  // ... and columns
 constexpr int STILE_S = STILE_C + 1;  // odd row stride (in doubles)
-constexpr double FLAT_IDZ = 1e300;    // stands for 1/Dz = infinity (|Z| FLAT_IDZ stays finite)
 
 template <int NI>
 struct SymTile {
