@@ -313,7 +313,9 @@ constexpr int STILE_S = STILE_C + 1;  // odd row stride (in doubles)
 
 template <int NI>
 struct SymTile {
-    double rt[NI][(STILE_R + 1) * STILE_S];  // each image's r |D|, [row - R0][col - C0]; row STILE_R: 0
+    // r |D| of images 2p and 2p + 1 at [row - R0][col - C0] (one 16-byte LDS
+    // read serves both); row STILE_R: 0
+    double2 rt[NI / 2][(STILE_R + 1) * STILE_S];
     double Sx[STILE_C], Sy[STILE_C], iDx[STILE_C], iDy[STILE_C], ox[STILE_C], oy[STILE_C];
     double iDz[STILE_R + 1];
 };
@@ -333,8 +335,11 @@ __device__ __forceinline__ void sym_row(const SymTile<NI> &S, int rel, int cc, d
     const double lo = fmax(tl, fmin(t0, t1)), hi = fmin(th, fmax(t0, t1));
     const double len = fmax(hi - lo, 0.0);
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
-        acc[i][k] = fma(len, S.rt[i][o], acc[i][k]);
+    for (int i = 0; i < NI / 2; ++i) {
+        const double2 v = S.rt[i][o];
+        acc[2 * i][k] = fma(len, v.x, acc[2 * i][k]);
+        acc[2 * i + 1][k] = fma(len, v.y, acc[2 * i + 1][k]);
+    }
 }
 
 // The cone-beam gather of gather_cone_tile for the cell's voxels iz0 ..
@@ -422,8 +427,8 @@ __device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T 
     const int vstep = g.nviews / ROT;
     for (int i = tid; i < STILE_S; i += BP_THREADS) {  // the zero rows
 #pragma unroll
-        for (int q = 0; q < NI; ++q)
-            S.rt[q][STILE_R * STILE_S + i] = 0.0;
+        for (int q = 0; q < NI / 2; ++q)
+            S.rt[q][STILE_R * STILE_S + i] = make_double2(0.0, 0.0);
     }
     if (tid == 0)
         S.iDz[STILE_R] = 1.0;
@@ -452,9 +457,15 @@ __device__ __forceinline__ void backproject_sym_block(const GeomDev &g, const T 
 #pragma unroll
             for (int q = 0; q < ROT; ++q) {
                 const T *rq = r + (size_t)vq * view_stride;
-                S.rt[q * NM][o] = (double)rq[(size_t)row * g.cols + col] * dn;
-                if (MIR)
-                    S.rt[q * NM + 1][o] = (double)rq[(size_t)(g.rows - 1 - row) * g.cols + col] * dn;
+                const double a = (double)rq[(size_t)row * g.cols + col] * dn;
+                if (MIR) {
+                    S.rt[q][o] =
+                        make_double2(a, (double)rq[(size_t)(g.rows - 1 - row) * g.cols + col] * dn);
+                } else if (q % 2 == 0) {
+                    S.rt[q / 2][o].x = a;
+                } else {
+                    S.rt[q / 2][o].y = a;
+                }
                 vq += vstep;
                 vq -= vq >= g.nviews ? g.nviews : 0;
             }
