@@ -97,12 +97,13 @@ FP64_VEC_PEAK = 78.6e12     # flop/s, MI355X FP64 vector (= FP32 without packed 
 VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s
 # vector instructions per voxel step of the projector's walk loop (count of the
 # gfx950 code the build emits for the single-precision project_kernel of the
-# column ray tiles on volumes under 2 GiB: 89 per iteration of four steps.
-# Per step: 3 min for the segment end, the length, the compares and selects
-# that pick the moving axis and its byte-offset step, 3 adds and 3 FMAs for
-# the planes and next crossings, convert and accumulate; per iteration: the
-# exit test and the iteration bound.  The row tiles' walk takes 47 per two.)
-PROJECT_VALU_PER_STEP = 22.25
+# column ray tiles on volumes under 2 GiB: 81 per iteration of four steps.
+# Per step: 3 min for the segment end, the length, 2 compares, 5 selects and
+# an add that pick the moving axis and its byte-offset step (the y and z
+# moves from scalar lane-mask operations), 3 adds and 3 FMAs for the planes
+# and next crossings, convert and accumulate; per iteration: the exit test
+# (the step bound is scalar).  The row tiles' walk takes 44 per two.)
+PROJECT_VALU_PER_STEP = 20.25
 
 
 def log(msg: str) -> None:

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "host.hpp"
+#include "raywalk.hpp"
 
 namespace tvr {
 
@@ -386,11 +387,14 @@ tvreg_status batched_impl(int n, const tvreg_geometry *const *geoms, const void 
         le = launch_trial_grouped<T>(dprobs, fam(F_VOX), n, total[F_VOX], cs);
     if (le == hipSuccess)
         le = launch_transpose_grouped<T>(dprobs, fam(F_TR), n, total[F_TR], cs);
+    bool pj_buf = true;  // the walk's buffer-resource loads for every problem
+    for (int i = 0; i < n; ++i)
+        pj_buf = pj_buf && walk_buffer_ok(geoms[i]->g, sizeof(T));
     for (int f = F_PJ; f < F_COUNT; ++f)
         if (le == hipSuccess && total[f] > 0)
             le = launch_project_grouped<T>(dprobs, fam(f), n, total[f],
                                            PJ_FAMILY_WC[(f - F_PJ) / 4],
-                                           PJ_FAMILY_TY[(f - F_PJ) % 4], cs);
+                                           PJ_FAMILY_TY[(f - F_PJ) % 4], pj_buf, cs);
     if (le == hipSuccess)
         le = launch_finalize_grouped<T>(dprobs, n, cs);
     if (le == hipSuccess)

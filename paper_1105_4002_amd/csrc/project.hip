@@ -74,10 +74,14 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
                                               double *__restrict__ partials, int pstride,
                                               int bx, int by, int v, int bid)
 {
-    const int col = bx * WC + (int)threadIdx.x % WC;
-    const int row = (by * TY + (int)threadIdx.y) * RayTile<WC>::rows + (int)threadIdx.x / WC;
+    const int col0 = bx * WC + (int)threadIdx.x % WC;
+    const int row0 = (by * TY + (int)threadIdx.y) * RayTile<WC>::rows + (int)threadIdx.x / WC;
+    // a lane past the detector's edge walks the edge ray and writes nothing,
+    // so the walk runs outside any divergent branch
+    const bool live = col0 < g.cols && row0 < g.rows;
+    const int col = min(col0, g.cols - 1), row = min(row0, g.rows - 1);
     double red[2] = {0.0, 0.0};
-    if (col < g.cols && row < g.rows) {
+    {
         ColEntry ce;
         RowEntry re;
         if (g.beam3d) {  // launch-uniform
@@ -101,16 +105,18 @@ __device__ __forceinline__ void project_block(const GeomDev &g, const T *__restr
         }
         const double s = ray_walk<T, CONE, BUF, sizeof(T) == 4 && column_tiles(WC)>(
             g, xs, ce, re, sx, sy, sz);
-        const double dn = CONE ? g.dnorm[(size_t)row * g.cols + col] : g.dnorm[v];
-        const size_t i = ((size_t)v * g.rows + row) * g.cols + col;
-        double ri = s * dn;
-        if (b)
-            ri -= (double)b[i];
-        out[i] = (T)ri;
-        red[0] = ri * ri;
-        if (rref) {
-            const double d = ri - (double)rref[i];
-            red[1] = d * d;
+        if (live) {
+            const double dn = CONE ? g.dnorm[(size_t)row * g.cols + col] : g.dnorm[v];
+            const size_t i = ((size_t)v * g.rows + row) * g.cols + col;
+            double ri = s * dn;
+            if (b)
+                ri -= (double)b[i];
+            out[i] = (T)ri;
+            red[0] = ri * ri;
+            if (rref) {
+                const double d = ri - (double)rref[i];
+                red[1] = d * d;
+            }
         }
     }
     if (partials) {
@@ -136,8 +142,9 @@ __global__ __launch_bounds__(64 * TY) void project_kernel(GeomDev g, const T *__
 
 // Batched: the trial points XB of every running problem (residual against
 // b, Bregman data term against RY), one launch per ray tile shape (WC
-// columns, TY waves) over the problems of that shape.
-template <typename T, int WC, int TY>
+// columns, TY waves) over the problems of that shape; BUF: every problem's
+// volume fits the buffer-resource loads.
+template <typename T, int WC, int TY, bool BUF>
 __global__ __launch_bounds__(64 * TY) void project_grouped(BatchProblem<T> *probs,
                                                           const int *offs, int n)
 {
@@ -149,64 +156,72 @@ __global__ __launch_bounds__(64 * TY) void project_grouped(BatchProblem<T> *prob
     int bx, by, v;
     decode_block(local, (P.g.cols + WC - 1) / WC, P.g.nviews, bx, by, v);
     if (P.g.cone)  // block-uniform
-        project_block<T, true, WC, TY, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
-                                              P.pstride, bx, by, v, local);
+        project_block<T, true, WC, TY, BUF>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
+                                            P.pstride, bx, by, v, local);
     else
-        project_block<T, false, WC, TY, false>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
-                                               P.pstride, bx, by, v, local);
+        project_block<T, false, WC, TY, BUF>(P.g, P.XB, P.XT, P.b, P.RXB, P.RY, P.part,
+                                             P.pstride, bx, by, v, local);
 }
 
-template <typename T, int WC>
+template <typename T, int WC, bool BUF>
 hipError_t launch_grouped_wc(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                              int waves, hipStream_t st)
 {
     switch (waves) {
     case 1:
-        hipLaunchKernelGGL((project_grouped<T, WC, 1>), dim3(blocks), dim3(64, 1), 0, st, probs,
+        hipLaunchKernelGGL((project_grouped<T, WC, 1, BUF>), dim3(blocks), dim3(64, 1), 0, st, probs,
                            offs, n);
         break;
     case 2:
-        hipLaunchKernelGGL((project_grouped<T, WC, 2>), dim3(blocks), dim3(64, 2), 0, st, probs,
+        hipLaunchKernelGGL((project_grouped<T, WC, 2, BUF>), dim3(blocks), dim3(64, 2), 0, st, probs,
                            offs, n);
         break;
     case 8:
-        hipLaunchKernelGGL((project_grouped<T, WC, 8>), dim3(blocks), dim3(64, 8), 0, st, probs,
+        hipLaunchKernelGGL((project_grouped<T, WC, 8, BUF>), dim3(blocks), dim3(64, 8), 0, st, probs,
                            offs, n);
         break;
     default:
-        hipLaunchKernelGGL((project_grouped<T, WC, 4>), dim3(blocks), dim3(64, 4), 0, st, probs,
+        hipLaunchKernelGGL((project_grouped<T, WC, 4, BUF>), dim3(blocks), dim3(64, 4), 0, st, probs,
                            offs, n);
         break;
     }
     return hipGetLastError();
 }
 
+template <typename T, bool BUF>
+hipError_t launch_grouped_buf(BatchProblem<T> *probs, const int *offs, int n, int blocks,
+                              int cols, int waves, hipStream_t st)
+{
+    switch (cols) {
+    case 1:
+        return launch_grouped_wc<T, 1, BUF>(probs, offs, n, blocks, waves, st);
+    case 2:
+        return launch_grouped_wc<T, 2, BUF>(probs, offs, n, blocks, waves, st);
+    case 8:
+        return launch_grouped_wc<T, 8, BUF>(probs, offs, n, blocks, waves, st);
+    case 16:
+        return launch_grouped_wc<T, 16, BUF>(probs, offs, n, blocks, waves, st);
+    case 32:
+        return launch_grouped_wc<T, 32, BUF>(probs, offs, n, blocks, waves, st);
+    default:
+        return launch_grouped_wc<T, 64, BUF>(probs, offs, n, blocks, waves, st);
+    }
+}
+
 }  // namespace
 
 template <typename T>
 hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
-                                  int cols, int waves, hipStream_t st)
+                                  int cols, int waves, bool buf, hipStream_t st)
 {
-    switch (cols) {
-    case 1:
-        return launch_grouped_wc<T, 1>(probs, offs, n, blocks, waves, st);
-    case 2:
-        return launch_grouped_wc<T, 2>(probs, offs, n, blocks, waves, st);
-    case 8:
-        return launch_grouped_wc<T, 8>(probs, offs, n, blocks, waves, st);
-    case 16:
-        return launch_grouped_wc<T, 16>(probs, offs, n, blocks, waves, st);
-    case 32:
-        return launch_grouped_wc<T, 32>(probs, offs, n, blocks, waves, st);
-    default:
-        return launch_grouped_wc<T, 64>(probs, offs, n, blocks, waves, st);
-    }
+    return buf ? launch_grouped_buf<T, true>(probs, offs, n, blocks, cols, waves, st)
+               : launch_grouped_buf<T, false>(probs, offs, n, blocks, cols, waves, st);
 }
 
 template hipError_t launch_project_grouped<float>(BatchProblem<float> *, const int *, int, int,
-                                                  int, int, hipStream_t);
+                                                  int, int, bool, hipStream_t);
 template hipError_t launch_project_grouped<double>(BatchProblem<double> *, const int *, int, int,
-                                                   int, int, hipStream_t);
+                                                   int, int, bool, hipStream_t);
 
 namespace {
 

@@ -37,14 +37,19 @@ __device__ __forceinline__ double walk_step(double &t, double tmax, double &Xn, 
     // inside: tn is one of the three crossings, and if neither x's nor y's,
     // then z's
     const bool ax = tnx <= tn, ay = tny <= tn;
-    const bool axy = ax || ay, my = ay && !ax;
+    // y moves where y is reached and x is not, z where neither is: both
+    // formed from the wave's lane masks of the two compares (scalar mask
+    // operations, no further per-lane compare or select)
+    const uint64_t bx = __builtin_amdgcn_ballot_w64(ax), by = __builtin_amdgcn_ballot_w64(ay);
+    const bool my = __builtin_amdgcn_inverse_ballot_w64(by & ~bx);
+    const bool az = __builtin_amdgcn_inverse_ballot_w64(~(bx | by));
     idx += ax ? stx : (ay ? sty : stz);
     // the moving axis steps to its next plane and the others add 0; all
     // three crossings are then recomputed, an unmoved plane giving its
     // previous crossing again bit for bit
     Xn += __hiloint2double(ax ? hx : 0, 0);
     Yn += __hiloint2double(my ? hy : 0, 0);
-    Zn += __hiloint2double(axy ? 0 : hz, 0);
+    Zn += __hiloint2double(az ? hz : 0, 0);
     tnx = plane_t(Xn, ivx, ox);
     tny = plane_t(Yn, ivy, oy);
     tnz = plane_t(Zn, ivz, oz);
@@ -87,17 +92,17 @@ __device__ __forceinline__ double ray_walk_sum(const GeomDev &g, const ColEntry 
     slab(lox, g.hx, ce.Sx, ce.invDx, ce.ox, tmin, tmax, hit);
     slab(loy, g.hy, ce.Sy, ce.invDy, ce.oy, tmin, tmax, hit);
     slab(loz, g.hz, re.Sz, re.invDz, re.oz, tmin, tmax, hit);
-    if (!hit || !(tmax > tmin))
-        return 0.0;
+    // a ray that misses the volume walks too (no divergent exit before the
+    // loop): its tmax is set to its start below, so every step has length 0
+    const bool ok = hit && (tmax > tmin);
 
     // entry voxel (an axis the ray runs parallel to keeps its coordinate;
-    // the clamp absorbs rounding at the entry face)
-    int ix = (int)floor((ce.invDx != 0.0 ? ce.Sx + tmin * ce.Dx : ce.Sx) - lox);
-    int iy = (int)floor((ce.invDy != 0.0 ? ce.Sy + tmin * ce.Dy : ce.Sy) - loy);
-    int iz = (int)floor((re.invDz != 0.0 ? re.Sz + tmin * re.Dz : re.Sz) - loz);
-    ix = min(max(ix, 0), g.nx - 1);
-    iy = min(max(iy, 0), g.ny - 1);
-    iz = min(max(iz, 0), g.nz - 1);
+    // the clamp absorbs rounding at the entry face, and keeps a missing
+    // ray's far-off point in range before its conversion to int)
+    const auto cell = [](double c, int n) { return (int)fmin(fmax(floor(c), 0.0), n - 1.0); };
+    const int ix = cell((ce.invDx != 0.0 ? ce.Sx + tmin * ce.Dx : ce.Sx) - lox, g.nx);
+    const int iy = cell((ce.invDy != 0.0 ? ce.Sy + tmin * ce.Dy : ce.Sy) - loy, g.ny);
+    const int iz = cell((re.invDz != 0.0 ? re.Sz + tmin * re.Dz : re.Sz) - loz, g.nz);
 
     // directions of travel (true: increasing index) and the index steps
     const bool px = ce.Dx > 0.0, py = ce.Dy > 0.0, pz = re.Dz > 0.0;
@@ -125,6 +130,8 @@ __device__ __forceinline__ double ray_walk_sum(const GeomDev &g, const ColEntry 
     // lengths are >= 0; the first crossing may round to before tmin, and
     // starting t at the smaller of the two gives that segment length 0.
     double t = fmin(tmin, fmin(fmin(tnx, tny), fmin(tnz, tmax)));
+    if (!ok)
+        tmax = t;
     // hard bound on the steps: each moves one plane, at most n - 1 per axis
     // before the exit crossing
     const int cap = g.nx + g.ny + g.nz + 2;
@@ -135,10 +142,11 @@ __device__ __forceinline__ double ray_walk_sum(const GeomDev &g, const ColEntry 
         // xa and xb; the wave leaves once none of its rays is still inside
         // after the fourth (a ray that left earlier adds steps of length 0)
         double xa = fetch(at(idx)), xb;
-        for (int it = 0; it < cap; it += 4) {
+        for (int it = 0;;) {
             bool inside;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            // (two calls, not a loop: the steps' lane-mask operations keep
+            // a compiler from unrolling one)
+            const auto two = [&]() {
                 const double d1 = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty,
                                             stz, hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox,
                                             oy, oz, inside);
@@ -149,19 +157,30 @@ __device__ __forceinline__ double ray_walk_sum(const GeomDev &g, const ColEntry 
                                             oy, oz, inside);
                 xa = fetch(at(idx));
                 acc = fma(d2, xb, acc);
-            }
-            if (!__any(inside))
+            };
+            two();
+            two();
+            // one exit test for both conditions (a single uniform branch
+            // keeps the step count in a scalar register)
+            it += 4;
+            if (!((__any(inside) != 0) & (it < cap)))
                 break;
         }
     } else {
-#pragma unroll 2
-        for (int it = 0; it < cap; ++it) {
+        bool inside = true;
+        const auto one = [&]() {
             const unsigned cur = at(idx);
-            bool inside;
             const double dt = walk_step(t, tmax, Xn, Yn, Zn, tnx, tny, tnz, idx, stx, sty, stz,
                                         hx, hy, hz, ce.invDx, ce.invDy, re.invDz, ox, oy, oz,
                                         inside);
             acc = fma(dt, fetch(cur), acc);
+        };
+        // two steps per iteration, called twice as above
+        for (int it = 0; it < cap; it += 2) {
+            one();
+            if (!inside)
+                break;
+            one();
             if (!inside)
                 break;
         }

@@ -328,9 +328,10 @@ template <typename T>
 hipError_t launch_transpose_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
                                     hipStream_t st);
 // the problems whose ray tile is `cols` columns x `waves` waves per block
+// (buf: every problem's volume fits the walk's buffer-resource loads)
 template <typename T>
 hipError_t launch_project_grouped(BatchProblem<T> *probs, const int *offs, int n, int blocks,
-                                  int cols, int waves, hipStream_t st);
+                                  int cols, int waves, bool buf, hipStream_t st);
 template <typename T>
 hipError_t launch_extrapolate_grouped(BatchProblem<T> *probs, const int *offs, int n,
                                       int blocks, hipStream_t st);
