@@ -51,12 +51,16 @@ HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 # one measured, and the projector's only at the measured ray tile
 # (profiles/cone256_kernels_hbm_traffic_pmc.md).
 MEASURED_TRAFFIC = [
-    # project_kernel<float, cone, 2 columns, 4 waves> (z-fastest companion):
-    # 2444822.0 + 107994.3 KiB
+    # project_kernel<float, cone, 2 columns, 8 or 4 waves> (z-fastest
+    # companion): 2393131.5 + 105130.0 and 2428391.0 + 109564.7 KiB
+    {"kernel": "project", "stored": None, "tile": (2, 8),
+     "sources": ["paper_1105_4002_amd/csrc/project.hip",
+                 "paper_1105_4002_amd/csrc/raywalk.hpp"],
+     "sha256_prefix": "39eaafeffd2d100e", "bytes": (2 * 2393131.5 + 105130.0) * 1024},
     {"kernel": "project", "stored": None, "tile": (2, 4),
      "sources": ["paper_1105_4002_amd/csrc/project.hip",
                  "paper_1105_4002_amd/csrc/raywalk.hpp"],
-     "sha256_prefix": "8c9fac026a898787", "bytes": (2 * 2444822.0 + 107994.3) * 1024},
+     "sha256_prefix": "39eaafeffd2d100e", "bytes": (2 * 2428391.0 + 109564.7) * 1024},
     # backproject_sym_kernel<float, quarter turns, z mirror, 4 deep>: 49026.9 + 66366.9 KiB
     {"kernel": "backproject", "stored": False, "tile": None,
      "sources": ["paper_1105_4002_amd/csrc/backproject.hip",
