@@ -63,71 +63,27 @@ __device__ __forceinline__ C huber_bregman(C a0, C a1, C a2, C b0, C b1, C b2, C
     return C(0.5) * (e0 * e0 + e1 * e1 + e2 * e2) * itau;
 }
 
-// One z-plane of a volume staged in LDS: columns [x0 - o, x0 - o + W) x
-// rows [y0 - o, y0 - o + H) of plane z, zero outside the volume; all the
-// block's threads take part.  The plane passes through registers so that its
-// global loads can be issued before the block's work on the current plane
-// and written to LDS after it (load_plane, then store_plane).
-template <typename T, int H, int W>
-struct PlaneRegs {
-    static constexpr int E = (H * W + VX * VY - 1) / (VX * VY);  // elements per thread
-    T v[E];
-};
-
-template <typename T, int H, int W>
-__device__ __forceinline__ void load_plane(const T *__restrict__ v, int nx, int ny, int x0, int y0,
-                                           int o, int z, PlaneRegs<T, H, W> &r)
-{
-    const size_t plane = (size_t)nx * ny * z;
-#pragma unroll
-    for (int k = 0; k < PlaneRegs<T, H, W>::E; ++k) {
-        const int e = thread_linear_id() + k * VX * VY;
-        const int ty = e / W, tx = e - ty * W;
-        const int gx = x0 - o + tx, gy = y0 - o + ty;
-        r.v[k] = (e < H * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-                     ? v[plane + (size_t)gy * nx + gx]
-                     : T(0);
-    }
-}
-
-template <typename T, int H, int W>
-__device__ __forceinline__ void store_plane(const PlaneRegs<T, H, W> &r, T (&tile)[H][W])
-{
-#pragma unroll
-    for (int k = 0; k < PlaneRegs<T, H, W>::E; ++k) {
-        const int e = thread_linear_id() + k * VX * VY;
-        if (e < H * W)
-            tile[e / W][e % W] = r.v[k];
-    }
-}
-
-template <typename T, int H, int W>
-__device__ __forceinline__ void stage_plane(const T *__restrict__ v, int nx, int ny, int x0,
-                                            int y0, int o, int z, T (&tile)[H][W])
-{
-    PlaneRegs<T, H, W> r;
-    load_plane(v, nx, ny, x0, y0, o, z, r);
-    store_plane(r, tile);
-}
-
 // gout = (gin ? gin : 0) + alpha grad T(y); with partials also the sums
 // T(y) and, with xref, Bregman_T(xref, y) and |xref - y|^2.  The block's
-// 64 x 4 columns march up VZ planes; each plane of y (with a one-voxel halo
-// on the low sides for the left and front neighbours' terms and on the high
-// sides for the forward differences) and of xref is staged once in LDS,
-// double-buffered against the next plane, so every neighbour is an LDS read.
+// 64 x 4 columns march up VZ planes.  Each thread reads the neighbours its
+// terms need (+x, +y, +z for its own forward differences; the left voxel's
+// +y and +z, the front voxel's +x and +z for their q components) straight
+// from global memory, where L1 and L2 serve the re-reads of adjacent
+// columns: no LDS staging and no barrier.  The values of plane z + 1 that
+// plane z already needs (own, left and front) are carried up; the next
+// plane's other loads are issued before the current plane's arithmetic.
+// Neighbours outside the volume read as 0 and only enter through the same
+// masks as the forward differences, so every voxel's arithmetic and every
+// block's sum order are those of a zero-padded volume.
 template <typename T>
 __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, double alpha,
-                                         const T *__restrict__ y, const T *__restrict__ xref,
-                                         const T *__restrict__ gin, T *__restrict__ gout,
-                                         double *__restrict__ partials, int pstride, int bx,
-                                         int by, int bz, int bid, bool value)
+                                                const T *__restrict__ y, const T *__restrict__ xref,
+                                                const T *__restrict__ gin, T *__restrict__ gout,
+                                                double *__restrict__ partials, int pstride, int bx,
+                                                int by, int bz, int bid, bool value)
 {
-    __shared__ T ys[2][VY + 2][VX + 2];  // x in [x0 - 1, x0 + VX], y in [y0 - 1, y0 + VY]
-    __shared__ T xs[2][VY + 1][VX + 1];  // x in [x0, x0 + VX], y in [y0, y0 + VY]
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int x0 = bx * VX, y0 = by * VY;
-    const int ix = x0 + tx, iy = y0 + ty;
+    const int ix = bx * VX + tx, iy = by * VY + ty;
     const int z0 = bz * VZ;
     const int z1 = min(z0 + VZ, nz);
     const bool active = ix < nx && iy < ny;
@@ -135,7 +91,8 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
     const T ct = (T)tau, itau = T(1) / ct;
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
     const bool hx = ix + 1 < nx, hy = iy + 1 < ny, lx = ix > 0, ly = iy > 0;
-    // z component of q at the voxel below the chunk
+    const bool hxly = hx && ly, lxhy = lx && hy;
+    const bool hasx = xref != nullptr, addg = gin != nullptr && gout != nullptr;
     T qz_prev = T(0);
     if (active && z0 > 0) {
         const size_t jb = (size_t)ix + sy * iy + sz * (z0 - 1);
@@ -145,94 +102,112 @@ __device__ __forceinline__ void tv_block(int nx, int ny, int nz, double tau, dou
         const T dz = y[jb + sz] - yb;
         qz_prev = dz * SM<T>::inv_clamped(dx * dx + dy * dy + dz * dz, ct, itau);
     }
-    // planes z and z + 1 sit in the two buffers while plane z is worked on;
-    // plane z + 2 is loaded meanwhile and replaces plane z afterwards
-    int cur = 0;
-    stage_plane(y, nx, ny, x0, y0, 1, z0, ys[0]);
-    if (xref)
-        stage_plane(xref, nx, ny, x0, y0, 0, z0, xs[0]);
-    if (z0 + 1 < nz) {
-        stage_plane(y, nx, ny, x0, y0, 1, z0 + 1, ys[1]);
-        if (xref)
-            stage_plane(xref, nx, ny, x0, y0, 0, z0 + 1, xs[1]);
-    }
-    PlaneRegs<T, VY + 2, VX + 2> ry;
-    PlaneRegs<T, VY + 1, VX + 1> rx;
-    // the gradient being added to, one plane ahead
-    const bool addg = gin != nullptr && gout != nullptr && active;
-    T gin_next = addg && z0 < z1 ? gin[(size_t)ix + sy * iy + sz * z0] : T(0);
-    for (int z = z0; z < z1; ++z) {
-        const int nxt = cur ^ 1;
-        const bool hz = z + 1 < nz;
-        const bool pre = z + 2 < nz && z + 2 <= z1;  // block-uniform: plane z + 2 is needed
-        __syncthreads();
-        if (pre) {
-            load_plane(y, nx, ny, x0, y0, 1, z + 2, ry);
-            if (xref)
-                load_plane(xref, nx, ny, x0, y0, 0, z + 2, rx);
+    const size_t j0 = active ? (size_t)ix + sy * iy + sz * z0 : 0;
+    // plane z values
+    T c = T(0), l = T(0), f = T(0), r = T(0), b = T(0), lb = T(0), rf = T(0);
+    T xj = T(0), xa = T(0), xb = T(0), g0 = T(0);
+    // plane z + 1 values
+    T cn = T(0), ln = T(0), fn = T(0), xc = T(0);
+    if (active && z0 < z1) {
+        const size_t j = j0;
+        c = y[j];
+        l = lx ? y[j - 1] : T(0);
+        f = ly ? y[j - sy] : T(0);
+        r = hx ? y[j + 1] : T(0);
+        b = hy ? y[j + sy] : T(0);
+        lb = lxhy ? y[j - 1 + sy] : T(0);
+        rf = hxly ? y[j + 1 - sy] : T(0);
+        if (hasx) {
+            xj = xref[j];
+            xa = hx ? xref[j + 1] : T(0);
+            xb = hy ? xref[j + sy] : T(0);
         }
-        const T gin_cur = gin_next;
-        if (addg && z + 1 < z1)
-            gin_next = gin[(size_t)ix + sy * iy + sz * (z + 1)];
+        if (addg)
+            g0 = gin[j];
+        if (z0 + 1 < nz) {
+            cn = y[j + sz];
+            ln = lx ? y[j + sz - 1] : T(0);
+            fn = ly ? y[j + sz - sy] : T(0);
+            if (hasx)
+                xc = xref[j + sz];
+        }
+    }
+    for (int z = z0; z < z1; ++z) {
+        const bool hz = z + 1 < nz;
+        const size_t j = j0 + sz * (size_t)(z - z0);
+        // next plane's lateral values and the plane after it, loaded ahead
+        T r1 = T(0), b1 = T(0), lb1 = T(0), rf1 = T(0), xa1 = T(0), xb1 = T(0), g1 = T(0);
+        T c2 = T(0), l2 = T(0), f2 = T(0), xc2 = T(0);
+        const bool nxt = active && z + 1 < z1;
+        if (nxt) {
+            const size_t k = j + sz;
+            r1 = hx ? y[k + 1] : T(0);
+            b1 = hy ? y[k + sy] : T(0);
+            lb1 = lxhy ? y[k - 1 + sy] : T(0);
+            rf1 = hxly ? y[k + 1 - sy] : T(0);
+            if (hasx) {
+                xa1 = hx ? xref[k + 1] : T(0);
+                xb1 = hy ? xref[k + sy] : T(0);
+            }
+            if (addg)
+                g1 = gin[k];
+            if (z + 2 < nz) {
+                const size_t k2 = k + sz;
+                c2 = y[k2];
+                l2 = lx ? y[k2 - 1] : T(0);
+                f2 = ly ? y[k2 - sy] : T(0);
+                if (hasx)
+                    xc2 = xref[k2];
+            }
+        }
         if (active) {
-            const T(&Y)[VY + 2][VX + 2] = ys[cur];
-            const T(&Yn)[VY + 2][VX + 2] = ys[nxt];
-            const int cx = tx + 1, cy = ty + 1;
-            const T yj = Y[cy][cx];
-            const T dx = hx ? Y[cy][cx + 1] - yj : T(0);
-            const T dy = hy ? Y[cy + 1][cx] - yj : T(0);
-            const T dz = hz ? Yn[cy][cx] - yj : T(0);
+            const T yj = c;
+            const T dx = hx ? r - yj : T(0);
+            const T dy = hy ? b - yj : T(0);
+            const T dz = hz ? cn - yj : T(0);
             const T d2 = dx * dx + dy * dy + dz * dz;
             const T inv = SM<T>::inv_clamped(d2, ct, itau);
             T gsum = -(dx + dy + dz) * inv + qz_prev;
             qz_prev = dz * inv;
-            {  // x component of q at the voxel on the left
-                const T yk = Y[cy][cx - 1];
+            {
+                const T yk = l;
                 const T ex = yj - yk;
-                const T ey = hy ? Y[cy + 1][cx - 1] - yk : T(0);
-                const T ez = hz ? Yn[cy][cx - 1] - yk : T(0);
+                const T ey = hy ? lb - yk : T(0);
+                const T ez = hz ? ln - yk : T(0);
                 const T t = ex * SM<T>::inv_clamped(ex * ex + ey * ey + ez * ez, ct, itau);
                 gsum += lx ? t : T(0);
             }
-            {  // y component of q at the voxel in front
-                const T yk = Y[cy - 1][cx];
-                const T ex = hx ? Y[cy - 1][cx + 1] - yk : T(0);
+            {
+                const T yk = f;
+                const T ex = hx ? rf - yk : T(0);
                 const T ey = yj - yk;
-                const T ez = hz ? Yn[cy - 1][cx] - yk : T(0);
+                const T ez = hz ? fn - yk : T(0);
                 const T t = ey * SM<T>::inv_clamped(ex * ex + ey * ey + ez * ez, ct, itau);
                 gsum += ly ? t : T(0);
             }
-            const size_t j = (size_t)ix + sy * iy + sz * z;
             if (gout)
-                gout[j] = gin ? (T)((double)gin_cur + alpha * (double)gsum)
+                gout[j] = gin ? (T)((double)g0 + alpha * (double)gsum)
                               : (T)(alpha * (double)gsum);
             if (partials) {
                 if (value)
                     red[0] += (double)huber_c<T>(d2, ct, itau);
-                if (xref) {
-                    const T(&X)[VY + 1][VX + 1] = xs[cur];
-                    const T xj = X[ty][tx];
+                if (hasx) {
                     const T ej = xj - yj;
-                    const T xa = X[ty][tx + 1], xb = X[ty + 1][tx], xc = xs[nxt][ty][tx];
                     const T a0 = hx ? xa - xj : T(0);
-                    const T e0 = hx ? (xa - Y[cy][cx + 1]) - ej : T(0);
+                    const T e0 = hx ? (xa - r) - ej : T(0);
                     const T a1 = hy ? xb - xj : T(0);
-                    const T e1 = hy ? (xb - Y[cy + 1][cx]) - ej : T(0);
+                    const T e1 = hy ? (xb - b) - ej : T(0);
                     const T a2 = hz ? xc - xj : T(0);
-                    const T e2 = hz ? (xc - Yn[cy][cx]) - ej : T(0);
+                    const T e2 = hz ? (xc - cn) - ej : T(0);
                     red[1] += (double)huber_bregman<T>(a0, a1, a2, dx, dy, dz, e0, e1, e2, ct, itau);
                     const double ed = (double)xj - (double)yj;
                     red[2] += ed * ed;
                 }
             }
         }
-        __syncthreads();  // every read of plane z is done: its buffer takes plane z + 2
-        if (pre) {
-            store_plane(ry, ys[cur]);
-            if (xref)
-                store_plane(rx, xs[cur]);
-        }
-        cur = nxt;
+        c = cn; l = ln; f = fn; xj = xc;
+        r = r1; b = b1; lb = lb1; rf = rf1; xa = xa1; xb = xb1; g0 = g1;
+        cn = c2; ln = l2; fn = f2; xc = xc2;
     }
     if (partials && value) {
         const int slots[3] = {S_TVY, S_BRY, S_XY2};
@@ -293,10 +268,10 @@ __device__ __forceinline__ T pstep(T z, T g, double step, const Box &box)
 
 // xbar = P_Q(z - step g) (Q = [lo, hi]^N, a clip) with the sums |xbar - z|^2,
 // g^T (z - xbar), T(xbar), Bregman_T(xbar, z) and, for gm_step > 0,
-// |z - P_Q(z - gm_step g)|^2 (the GPBB gradient map).  Planes of z and g
-// (with the high-side halo the forward differences need) are staged in LDS
-// as in the TV stencil, two buffers deep with the plane after next loaded
-// into registers while the current one is worked on.
+// |z - P_Q(z - gm_step g)|^2 (the GPBB gradient map).  As in the TV stencil
+// each thread reads its high-side neighbours of z and g from global memory
+// with no barrier, the next plane's loads issued before the current plane's
+// arithmetic; the value above becomes the next plane's own.
 template <typename T>
 __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
                                             const T *__restrict__ zv, const T *__restrict__ g,
@@ -304,11 +279,7 @@ __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
                                             T *__restrict__ xbar, double *__restrict__ partials,
                                             int pstride, int bx, int by, int bz, int bid)
 {
-    __shared__ T zs[2][VY + 1][VX + 1];  // x in [x0, x0 + VX], y in [y0, y0 + VY]
-    __shared__ T gs[2][VY + 1][VX + 1];
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int x0 = bx * VX, y0 = by * VY;
-    const int ix = x0 + tx, iy = y0 + ty;
+    const int ix = bx * VX + (int)threadIdx.x, iy = by * VY + (int)threadIdx.y;
     const int z0 = bz * VZ;
     const int z1 = min(z0 + VZ, nz);
     const bool active = ix < nx && iy < ny;
@@ -316,35 +287,54 @@ __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
     const T ct = (T)tau, itau = T(1) / ct;
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
     const bool hx = ix + 1 < nx, hy = iy + 1 < ny;
-    int cur = 0;
-    stage_plane(zv, nx, ny, x0, y0, 0, z0, zs[0]);
-    stage_plane(g, nx, ny, x0, y0, 0, z0, gs[0]);
-    if (z0 + 1 < nz) {
-        stage_plane(zv, nx, ny, x0, y0, 0, z0 + 1, zs[1]);
-        stage_plane(g, nx, ny, x0, y0, 0, z0 + 1, gs[1]);
+    const size_t j0 = active ? (size_t)ix + sy * iy + sz * z0 : 0;
+    // plane z: own, +x and +y values; plane z + 1: own value
+    T zc = T(0), gc = T(0), zr = T(0), gr = T(0), zb = T(0), gb = T(0), zn = T(0), gn = T(0);
+    if (active && z0 < z1) {
+        zc = zv[j0];
+        gc = g[j0];
+        if (hx) {
+            zr = zv[j0 + 1];
+            gr = g[j0 + 1];
+        }
+        if (hy) {
+            zb = zv[j0 + sy];
+            gb = g[j0 + sy];
+        }
+        if (z0 + 1 < nz) {
+            zn = zv[j0 + sz];
+            gn = g[j0 + sz];
+        }
     }
-    PlaneRegs<T, VY + 1, VX + 1> rz, rg;
     for (int z = z0; z < z1; ++z) {
-        const int nxt = cur ^ 1;
         const bool hz = z + 1 < nz;
-        const bool pre = z + 2 < nz && z + 2 <= z1;  // block-uniform
-        __syncthreads();
-        if (pre) {
-            load_plane(zv, nx, ny, x0, y0, 0, z + 2, rz);
-            load_plane(g, nx, ny, x0, y0, 0, z + 2, rg);
+        const size_t j = j0 + sz * (size_t)(z - z0);
+        T zr1 = T(0), gr1 = T(0), zb1 = T(0), gb1 = T(0), zn2 = T(0), gn2 = T(0);
+        if (active && z + 1 < z1) {
+            const size_t k = j + sz;
+            if (hx) {
+                zr1 = zv[k + 1];
+                gr1 = g[k + 1];
+            }
+            if (hy) {
+                zb1 = zv[k + sy];
+                gb1 = g[k + sy];
+            }
+            if (z + 2 < nz) {
+                zn2 = zv[k + sz];
+                gn2 = g[k + sz];
+            }
         }
         if (active) {
-            const T(&Z)[VY + 1][VX + 1] = zs[cur];
-            const T(&Gc)[VY + 1][VX + 1] = gs[cur];
-            const T zj = Z[ty][tx], gj = Gc[ty][tx];
+            const T zj = zc, gj = gc;
             const T xj = pstep(zj, gj, step, box);
-            const T zxp = hx ? Z[ty][tx + 1] : zj;
-            const T xxp = hx ? pstep(zxp, Gc[ty][tx + 1], step, box) : xj;
-            const T zyp = hy ? Z[ty + 1][tx] : zj;
-            const T xyp = hy ? pstep(zyp, Gc[ty + 1][tx], step, box) : xj;
-            const T zzp = hz ? zs[nxt][ty][tx] : zj;
-            const T xzp = hz ? pstep(zzp, gs[nxt][ty][tx], step, box) : xj;
-            xbar[(size_t)ix + sy * iy + sz * z] = xj;
+            const T zxp = hx ? zr : zj;
+            const T xxp = hx ? pstep(zxp, gr, step, box) : xj;
+            const T zyp = hy ? zb : zj;
+            const T xyp = hy ? pstep(zyp, gb, step, box) : xj;
+            const T zzp = hz ? zn : zj;
+            const T xzp = hz ? pstep(zzp, gn, step, box) : xj;
+            xbar[j] = xj;
             const double ed = (double)xj - (double)zj;
             red[0] += ed * ed;
             red[1] -= (double)gj * ed;
@@ -360,12 +350,14 @@ __device__ __forceinline__ void trial_block(int nx, int ny, int nz, double tau,
                 red[4] += p * p;
             }
         }
-        __syncthreads();  // every read of plane z is done: its buffers take plane z + 2
-        if (pre) {
-            store_plane(rz, zs[cur]);
-            store_plane(rg, gs[cur]);
-        }
-        cur = nxt;
+        zc = zn;
+        gc = gn;
+        zr = zr1;
+        gr = gr1;
+        zb = zb1;
+        gb = gb1;
+        zn = zn2;
+        gn = gn2;
     }
     const int slots[5] = {S_XD2, S_GD, S_TVB, S_BRB, S_GM2};
     block_reduce_store<5>(red, partials, pstride, slots, bid);
